@@ -1,0 +1,177 @@
+/*
+ * ftgemm.h -- C ABI of the online fault-tolerant GEMM library for AMD MI355X
+ * (gfx950).
+ *
+ * The library computes C = alpha * A * B + beta * C with algorithm-based fault
+ * tolerance fused into the GEMM main loop, following Wu et al., "Anatomy of
+ * High-Performance GEMM with Online Fault Tolerance on GPUs" (ICS'23,
+ * arXiv:2305.01024):
+ *   - checksum encodings e^T A (column checksums of A) and B e (row checksums
+ *     of B), section 2.2, Eq. 1-2, carried as the reference checksums of the
+ *     product (Eq. 3);
+ *   - the outer-product online form (section 2.2, Eq. 4): the checksum
+ *     relation is maintained after every k-step update, so each output tile
+ *     is checked during the k-loop and at its end (threadblock-level ABFT,
+ *     section 4.2.3);
+ *   - a single faulty accumulator element per tile and check interval (the
+ *     single-event-upset model of section 4.1) is located at the intersection
+ *     of the offending row and column and corrected from the checksum
+ *     (section 4.2.1, section 5.3).
+ * The detection threshold, which the paper leaves as "a predetermined
+ * threshold", is the analytic FP32 roundoff bound
+ *     tau_row_i = c * 2u (K' + n_J + 1) * ||a_i[0:K']|| * sum_{j in J} ||b_j[0:K']||
+ *     tau_col_j = c * 2u (K' + m_I + 1) * ||b_j[0:K']|| * sum_{i in I} ||a_i[0:K']||
+ * with u = 2^-24, K' the k indices accumulated so far, (m_I, n_J) the valid
+ * extent of the tile and c the tolerance factor (default 2).
+ *
+ * Conventions (BLAS, column-major, no transposes): A is m x k with leading
+ * dimension lda >= max(1, m); B is k x n with ldb >= max(1, k); C is m x n with
+ * ldc >= max(1, m).  A, B and C are device pointers on the handle's device,
+ * owned by the caller.  Every call is asynchronous on the given HIP stream
+ * unless a report is requested (then it synchronises that stream).
+ *
+ * Return codes: FTGEMM_OK (0); FTGEMM_UNCORRECTABLE (1, success with a
+ * warning: at least one tile saw more than one fault in a check interval, C
+ * may be wrong there and the events say where); negative values are errors
+ * listed in enum ftgemm_status.  A handle is not thread-safe; use one handle
+ * per stream.
+ */
+#ifndef FTGEMM_H
+#define FTGEMM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ftgemm_ctx* ftgemm_t;
+
+enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2 };
+
+/* ft_level: 0 = plain GEMM (fault tolerance compiled out of the kernel);
+ * 1 = detect only, one check of the accumulated tile at the end of the
+ *     k-loop (the offline, detect-only scheme of section 5.5);
+ * 2 = online detect + locate + correct, checks every check interval. */
+enum ftgemm_level { FTGEMM_FT_OFF = 0, FTGEMM_FT_DETECT = 1, FTGEMM_FT_CORRECT = 2 };
+
+enum ftgemm_status {
+    FTGEMM_OK = 0,
+    FTGEMM_UNCORRECTABLE = 1,
+    FTGEMM_INVALID = -1,       /* invalid argument; report->bad_arg names it */
+    FTGEMM_UNSUPPORTED = -2,   /* dtype, level or device not supported */
+    FTGEMM_HIP_ERROR = -3,     /* a HIP runtime call failed */
+    FTGEMM_NO_MEMORY = -4,     /* device or host allocation failed */
+    FTGEMM_LOG_OVERFLOW = -5   /* more events than the report can hold; counts stay exact */
+};
+
+enum ftgemm_event_kind {
+    FTGEMM_EV_CORRECTED = 1,      /* one row and one column flagged: element rebuilt */
+    FTGEMM_EV_CHECKSUM_ROW = 2,   /* one row flagged, no column: row checksum re-based */
+    FTGEMM_EV_CHECKSUM_COL = 3,   /* one column flagged, no row: column checksum re-based */
+    FTGEMM_EV_UNCORRECTABLE = 4,  /* any other pattern: checksums re-based, C left as computed */
+    FTGEMM_EV_DETECTED = 5        /* detect-only level: any flagged pattern */
+};
+
+enum ftgemm_fault_kind { FTGEMM_FAULT_ADD = 0, FTGEMM_FAULT_XOR = 1 };
+
+/* One detection event.  row/col are tile-relative (row index within the m
+ * range of the tile, column index within its n range); value_before/after are
+ * the accumulator element before and after correction (alpha/beta not yet
+ * applied). */
+typedef struct {
+    int32_t problem, tile_m, tile_n, kstep, row, col, kind, n_rows, n_cols, pad_;
+    float value_before, value_after, r_row, r_col, tau_row, tau_col;
+} ftgemm_event_t;
+
+/* A fault site for the injection hook: after the accumulator update of k-step
+ * `kstep`, element (row, col) of tile (tile_m, tile_n) of problem `problem`
+ * gets `+= payload` (FTGEMM_FAULT_ADD) or has bit (int)payload flipped
+ * (FTGEMM_FAULT_XOR). */
+typedef struct {
+    int32_t tile_m, tile_n, kstep, row, col, kind;
+    float payload;
+    int32_t problem;
+} ftgemm_fault_t;
+
+/* An applied fault: the site, the accumulator value before/after, and the
+ * residuals and thresholds of its row and column at the first check that saw
+ * it (check_step; -1 if no check ran after it). */
+typedef struct {
+    int32_t problem, tile_m, tile_n, kstep, row, col, kind, check_step;
+    float old_v, new_v, r_row, r_col, tau_row, tau_col, pad0_, pad1_;
+} ftgemm_fault_log_t;
+
+/* Kernel configuration: compute tile (= check tile) m_tile x n_tile, k-step
+ * k_step, a check every check_interval k-steps (and after the last). */
+typedef struct {
+    int32_t m_tile, n_tile, k_step, check_interval;
+} ftgemm_config_t;
+
+typedef struct {
+    uint64_t checks;          /* tile checks performed */
+    uint64_t detected;        /* checks that flagged anything */
+    uint64_t corrected;       /* FTGEMM_EV_CORRECTED events */
+    uint64_t uncorrectable;   /* FTGEMM_EV_UNCORRECTABLE events */
+    uint64_t checksum_only;   /* FTGEMM_EV_CHECKSUM_ROW/COL events */
+    uint32_t n_events;        /* events written to `events` (<= cap_events) */
+    uint32_t cap_events;      /* set by the caller: capacity of `events` */
+    ftgemm_event_t* events;   /* caller-owned host array, may be NULL */
+    ftgemm_config_t config;   /* configuration the call used */
+    int32_t bad_arg;          /* 1-based position of an invalid argument, else 0 */
+    float tol_used;           /* threshold factor c the call used */
+} ftgemm_report_t;
+
+/* Create a handle on `device` for operands of type `dtype`.  Allocates the
+ * device event log and counters.  Returns FTGEMM_UNSUPPORTED if the device is
+ * not gfx950. */
+int ftgemm_create(ftgemm_t* handle, int dtype, int device);
+int ftgemm_destroy(ftgemm_t handle);
+
+/* Per-tensor dequantisation scales for BF16/FP8 operands (default 1):
+ * the product is computed as (scale_a * A) (scale_b * B). */
+int ftgemm_set_scales(ftgemm_t handle, float scale_a, float scale_b);
+
+/* Force a kernel configuration for later calls (NULL: automatic selection).
+ * Returns FTGEMM_UNSUPPORTED if no kernel variant has that tile shape. */
+int ftgemm_set_config(ftgemm_t handle, const ftgemm_config_t* config);
+
+/* Host-only: the configuration automatic selection picks for a shape. */
+int ftgemm_select_config(int dtype, int64_t m, int64_t n, int64_t k, int ft_level,
+                         ftgemm_config_t* config);
+
+/* Host-only argument check used by ftgemm_run.  Returns FTGEMM_OK or
+ * FTGEMM_INVALID with *bad_arg set to the 1-based position of the offending
+ * ftgemm_run argument (2 = m, 3 = n, 4 = k, 7 = lda, 9 = ldb, 12 = ldc,
+ * 13 = ft_level, 14 = tol). */
+int ftgemm_validate(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc,
+                    int ft_level, float tol, int32_t* bad_arg);
+
+/* C = alpha * A * B + beta * C with fault tolerance level `ft_level`.
+ * tol <= 0 selects the default threshold factor c = 2; tol > 0 sets c.
+ * beta == 0: C is not read.  k == 0 or alpha == 0: C = beta * C.
+ * With report != NULL the call synchronises `stream` and fills the report
+ * (events up to report->cap_events).  Returns a status code. */
+int ftgemm_run(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, float beta,
+               float* C, int64_t ldc, int ft_level, float tol, hipStream_t stream,
+               ftgemm_report_t* report);
+
+/* Fault injection hook (compiled into dedicated kernel instantiations; the
+ * production kernels contain no injection code).  `faults` is a host array
+ * of n sites, copied to the device; n == 0 disables injection.  Sites must
+ * be sorted by (problem, tile_m, tile_n, kstep); at most 32 per tile. */
+int ftgemm_set_injection(ftgemm_t handle, const ftgemm_fault_t* faults, int n);
+
+/* Copy the applied-fault log of the last call into `out` (host array of cap
+ * entries); *n receives the number of faults applied. */
+int ftgemm_get_injection_log(ftgemm_t handle, ftgemm_fault_log_t* out, int cap, int* n);
+
+const char* ftgemm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTGEMM_H */

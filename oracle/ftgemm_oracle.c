@@ -33,6 +33,7 @@
  * in ascending k order.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -430,6 +431,9 @@ int64_t oracle_ftgemm_replay(const oracle_cfg_t* cfg,
     free(order);
     return total;
 }
+
+/* Number of OpenMP threads the oracle runs with (for reporting). */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ABI self-description used by the Python loader to check struct layouts. */
 int64_t oracle_sizeof(int which)

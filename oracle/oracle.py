@@ -106,6 +106,8 @@ def load(path: str | None = None):
     lib.oracle_ftgemm_replay.argtypes = [ctypes.POINTER(_Cfg), dp, i64, dp, i64, dp, i64, dp, i64,
                                          vp, i64, vp, i64, vp, vp, i64]
     lib.oracle_ftgemm_replay.restype = i64
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_sizeof.argtypes = [ctypes.c_int]
     lib.oracle_sizeof.restype = i64
     for which, want in ((0, ctypes.sizeof(_Cfg)), (1, INJ_DTYPE.itemsize), (2, EV_DTYPE.itemsize),
@@ -189,6 +191,11 @@ def encode_row(B) -> np.ndarray:
     v = np.zeros(B.shape[0], dtype=np.float64)
     lib.oracle_encode_row(B.shape[0], B.shape[1], _dp(B), max(B.shape[0], 1), _dp(v))
     return v
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(load().oracle_threads())
 
 
 def beta_bound(u, kprime, count, own_norm, other_norm_sum) -> float:

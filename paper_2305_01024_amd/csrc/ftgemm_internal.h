@@ -1,0 +1,61 @@
+// ftgemm_internal.h -- launch interface between the C ABI (ftgemm_api.cpp)
+// and the gfx950 kernels (ftgemm_fp32.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+#include "ftgemm.h"
+
+namespace ftgemm_impl {
+
+// Device-side counters, one block per handle (index into `counters`).
+enum Counter : int {
+    CNT_EVENTS = 0,        // events appended (may exceed capacity)
+    CNT_DETECTED = 1,
+    CNT_CORRECTED = 2,
+    CNT_UNCORRECTABLE = 3,
+    CNT_CHECKSUM_ONLY = 4,
+    CNT_FAULTS = 5,        // faults applied by the injection hook
+    CNT_N = 8
+};
+
+// Maximum fault sites one tile may hold in the injection build.
+constexpr int kMaxFaultsPerTile = 32;
+
+struct LaunchArgs {
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    float alpha, beta;
+    float tol_c;                 // threshold factor c
+    int32_t check_interval;      // g, in k-steps
+    int32_t ft_level;            // 0, 1, 2
+    int32_t problem;             // problem index reported in events
+    ftgemm_event_t* events;      // device event log
+    uint32_t* counters;          // device counters[CNT_N]
+    int32_t event_cap;
+    const ftgemm_fault_t* faults;    // device fault sites (injection build) or nullptr
+    int32_t n_faults;
+    ftgemm_fault_log_t* fault_log;   // device applied-fault log
+    int32_t fault_log_cap;
+};
+
+struct Variant {
+    int m_tile, n_tile, k_step;
+};
+
+// Kernel variants compiled for FP32 operands, in preference order.
+int fp32_variant_count();
+Variant fp32_variant(int idx);
+int fp32_find_variant(int m_tile, int n_tile, int k_step);
+
+// Launch the FP32 kernel variant `idx`.  `inject` selects the instantiation
+// carrying the fault-injection hook.  Returns a hipError_t.
+hipError_t launch_fp32(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+
+// C = beta * C (beta == 0 writes zeros without reading C).
+hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t stream);
+
+}  // namespace ftgemm_impl

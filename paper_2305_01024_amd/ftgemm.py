@@ -1,0 +1,177 @@
+"""Thin ctypes binding of the HIP library ``lib/libftgemm.so`` (C ABI in
+``include/ftgemm.h``).  Functions keep the C names and argument order; this
+module only marshals arguments (device pointers, sizes, host arrays for the
+report and the fault sites).  Every step of the computation runs in the HIP
+kernels: if the library is missing this module raises, there is no fallback.
+
+Device memory and streams come from PyTorch: pass ``tensor.data_ptr()`` for
+matrices and ``torch.cuda.current_stream().cuda_stream`` for the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libftgemm.so")
+
+F32, BF16, F8E4M3 = 0, 1, 2
+FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
+OK, UNCORRECTABLE, INVALID, UNSUPPORTED, HIP_ERROR, NO_MEMORY, LOG_OVERFLOW = 0, 1, -1, -2, -3, -4, -5
+EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED = 1, 2, 3, 4, 5
+FAULT_ADD, FAULT_XOR = 0, 1
+
+EVENT_DTYPE = np.dtype([("problem", "<i4"), ("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"),
+                        ("row", "<i4"), ("col", "<i4"), ("kind", "<i4"), ("n_rows", "<i4"),
+                        ("n_cols", "<i4"), ("pad_", "<i4"), ("value_before", "<f4"),
+                        ("value_after", "<f4"), ("r_row", "<f4"), ("r_col", "<f4"),
+                        ("tau_row", "<f4"), ("tau_col", "<f4")])
+FAULT_DTYPE = np.dtype([("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"), ("row", "<i4"),
+                        ("col", "<i4"), ("kind", "<i4"), ("payload", "<f4"), ("problem", "<i4")])
+FAULT_LOG_DTYPE = np.dtype([("problem", "<i4"), ("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"),
+                            ("row", "<i4"), ("col", "<i4"), ("kind", "<i4"), ("check_step", "<i4"),
+                            ("old_v", "<f4"), ("new_v", "<f4"), ("r_row", "<f4"), ("r_col", "<f4"),
+                            ("tau_row", "<f4"), ("tau_col", "<f4"), ("pad0_", "<f4"), ("pad1_", "<f4")])
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("m_tile", ctypes.c_int32), ("n_tile", ctypes.c_int32), ("k_step", ctypes.c_int32),
+                ("check_interval", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.m_tile, self.n_tile, self.k_step, self.check_interval)
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("checks", ctypes.c_uint64), ("detected", ctypes.c_uint64), ("corrected", ctypes.c_uint64),
+                ("uncorrectable", ctypes.c_uint64), ("checksum_only", ctypes.c_uint64),
+                ("n_events", ctypes.c_uint32), ("cap_events", ctypes.c_uint32),
+                ("events", ctypes.c_void_p), ("config", Config), ("bad_arg", ctypes.c_int32),
+                ("tol_used", ctypes.c_float)]
+
+
+class ReportBuffer:
+    """A Report plus the caller-owned host array its events are copied into."""
+
+    def __init__(self, cap: int = 4096):
+        self.events_buf = np.zeros(cap, dtype=EVENT_DTYPE)
+        self.report = Report()
+        self.report.cap_events = cap
+        self.report.events = self.events_buf.ctypes.data
+
+    @property
+    def events(self) -> np.ndarray:
+        return self.events_buf[: self.report.n_events].copy()
+
+    def ptr(self):
+        return ctypes.byref(self.report)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_01024_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+        L.ftgemm_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+        L.ftgemm_destroy.argtypes = [vp]
+        L.ftgemm_set_scales.argtypes = [vp, f32, f32]
+        L.ftgemm_set_config.argtypes = [vp, ctypes.POINTER(Config)]
+        L.ftgemm_select_config.argtypes = [i32, i64, i64, i64, i32, ctypes.POINTER(Config)]
+        L.ftgemm_validate.argtypes = [i64, i64, i64, i64, i64, i64, i32, f32, ctypes.POINTER(ctypes.c_int32)]
+        L.ftgemm_run.argtypes = [vp, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
+                                 ctypes.POINTER(Report)]
+        L.ftgemm_set_injection.argtypes = [vp, vp, i32]
+        L.ftgemm_get_injection_log.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.ftgemm_status_string.argtypes = [i32]
+        L.ftgemm_status_string.restype = ctypes.c_char_p
+        for name in ("ftgemm_create", "ftgemm_destroy", "ftgemm_set_scales", "ftgemm_set_config",
+                     "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
+                     "ftgemm_get_injection_log"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+class FtgemmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status} ({ftgemm_status_string(status)})")
+        self.status = status
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise FtgemmError(status, where)
+    return status
+
+
+def ftgemm_status_string(status: int) -> str:
+    return lib().ftgemm_status_string(status).decode()
+
+
+def ftgemm_create(dtype: int = F32, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().ftgemm_create(ctypes.byref(h), dtype, device), "ftgemm_create")
+    return h.value
+
+
+def ftgemm_destroy(handle: int) -> None:
+    _check(lib().ftgemm_destroy(handle), "ftgemm_destroy")
+
+
+def ftgemm_set_scales(handle: int, scale_a: float, scale_b: float) -> None:
+    _check(lib().ftgemm_set_scales(handle, scale_a, scale_b), "ftgemm_set_scales")
+
+
+def ftgemm_set_config(handle: int, config: Config | tuple | None) -> None:
+    if config is None:
+        _check(lib().ftgemm_set_config(handle, None), "ftgemm_set_config")
+        return
+    if not isinstance(config, Config):
+        config = Config(*config)
+    _check(lib().ftgemm_set_config(handle, ctypes.byref(config)), "ftgemm_set_config")
+
+
+def ftgemm_select_config(dtype: int, m: int, n: int, k: int, ft_level: int = FT_CORRECT) -> Config:
+    c = Config()
+    _check(lib().ftgemm_select_config(dtype, m, n, k, ft_level, ctypes.byref(c)), "ftgemm_select_config")
+    return c
+
+
+def ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level=FT_CORRECT, tol=0.0):
+    """Returns (status, bad_arg)."""
+    bad = ctypes.c_int32(0)
+    st = lib().ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level, tol, ctypes.byref(bad))
+    return st, bad.value
+
+
+def ftgemm_run(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: int, B: int, ldb: int,
+               beta: float, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
+               stream: int = 0, report: ReportBuffer | None = None) -> int:
+    """C = alpha A B + beta C on device pointers (column-major).  Returns the
+    status (0 or 1); raises FtgemmError on negative statuses."""
+    st = lib().ftgemm_run(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
+                          report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_run")
+
+
+def ftgemm_set_injection(handle: int, faults: np.ndarray | None) -> None:
+    if faults is None or len(faults) == 0:
+        _check(lib().ftgemm_set_injection(handle, None, 0), "ftgemm_set_injection")
+        return
+    arr = np.ascontiguousarray(faults, dtype=FAULT_DTYPE)
+    _check(lib().ftgemm_set_injection(handle, arr.ctypes.data, len(arr)), "ftgemm_set_injection")
+
+
+def ftgemm_get_injection_log(handle: int, cap: int = 16384) -> np.ndarray:
+    out = np.zeros(cap, dtype=FAULT_LOG_DTYPE)
+    n = ctypes.c_int(0)
+    _check(lib().ftgemm_get_injection_log(handle, out.ctypes.data, cap, ctypes.byref(n)),
+           "ftgemm_get_injection_log")
+    return out[: min(n.value, cap)].copy()

@@ -23,7 +23,7 @@ KIND_ADD = 0   # accumulator += payload
 KIND_XOR = 1   # accumulator bits ^= 1 << payload
 
 SITE_DTYPE = np.dtype([("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"), ("row", "<i4"),
-                       ("col", "<i4"), ("kind", "<i4"), ("payload", "<f4"), ("pad_", "<i4")])
+                       ("col", "<i4"), ("kind", "<i4"), ("payload", "<f4"), ("problem", "<i4")])
 
 
 def seed(workload: int, stream: int) -> int:

@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/ftgemm.h declares, its structs have the sizes the binding
+assumes, and the host-only entry points (argument validation, configuration
+selection, status strings) behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2305_01024_amd import ftgemm as F
+from paper_2305_01024_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ftgemm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ftgemm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    assert os.path.exists(F.LIB_PATH), "build the library first"
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (ftgemm_\w+)", out))
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    lib = F.lib()
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_struct_sizes_match_header_layout():
+    # sizes implied by include/ftgemm.h on LP64
+    assert F.EVENT_DTYPE.itemsize == 64
+    assert F.FAULT_DTYPE.itemsize == 32
+    assert F.FAULT_LOG_DTYPE.itemsize == 64
+    assert ctypes.sizeof(F.Config) == 16
+    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4
+    assert W.SITE_DTYPE == F.FAULT_DTYPE
+
+
+@pytest.mark.parametrize("args,bad", [
+    ((-1, 4, 4, 4, 4, 4), 2),
+    ((4, -1, 4, 4, 4, 4), 3),
+    ((4, 4, -1, 4, 4, 4), 4),
+    ((4, 4, 4, 3, 4, 4), 7),
+    ((4, 4, 4, 4, 3, 4), 9),
+    ((4, 4, 4, 4, 4, 3), 12),
+    ((0, 0, 0, 1, 1, 1), 0),
+    ((5, 7, 0, 5, 1, 5), 0),
+    ((2 ** 31, 4, 4, 2 ** 31, 4, 2 ** 31), 2),
+])
+def test_validate_reports_blas_argument_positions(args, bad):
+    st, got = F.ftgemm_validate(*args)
+    assert got == bad
+    assert st == (F.OK if bad == 0 else F.INVALID)
+
+
+def test_validate_level_and_tol():
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=3)[1] == 13
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=-1)[1] == 13
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, tol=float("nan"))[1] == 14
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, tol=-1.0)[1] == 0   # <= 0 selects the default
+
+
+def test_select_config_fills_the_gpu_and_checks_every_256_k():
+    for (m, n) in [(8192, 8192), (4096, 4096), (2048, 2048), (65536, 256), (256, 65536), (3001, 1999),
+                   (100, 100)]:
+        c = F.ftgemm_select_config(F.F32, m, n, 1024)
+        tiles = -(-m // c.m_tile) * -(-n // c.n_tile)
+        assert c.k_step * c.check_interval == 256
+        assert tiles >= 256 or (c.m_tile, c.n_tile) == (64, 64), (m, n, c.as_tuple())
+    assert F.ftgemm_select_config(F.F32, 8192, 8192, 8192).as_tuple()[:2] == (256, 256)
+    assert F.ftgemm_select_config(F.F32, 2048, 2048, 2048).as_tuple()[:2] == (128, 128)
+
+
+def test_status_strings():
+    assert F.ftgemm_status_string(F.OK) == "ok"
+    assert "invalid" in F.ftgemm_status_string(F.INVALID)
+
+
+def test_run_with_null_handle_is_invalid_not_a_crash():
+    rep = F.ReportBuffer(4)
+    st = F.lib().ftgemm_run(None, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 2, 0.0, None, rep.ptr())
+    assert st == F.INVALID and rep.report.bad_arg == 1
+
+
+def test_create_without_gfx950_is_unsupported():
+    """On a host with no gfx950 device the handle is refused, not faked."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert F.lib().ftgemm_create(ctypes.byref(h), F.F32, 0) == F.UNSUPPORTED
+    assert h.value is None
+
+
+def test_fault_sites_respect_one_per_tile_interval():
+    g = np.random.default_rng(7)
+    m, n, k, mc, nc, ku, gi = 600, 500, 1000, 128, 128, 32, 8
+    sites = W.fault_sites(g, m, n, k, mc, nc, ku, gi, count=60, kind=W.KIND_XOR)   # 80 slots
+    key = set()
+    nk = -(-k // ku)
+    for s in sites:
+        tile_rows = min(mc, m - s["tile_m"] * mc)
+        tile_cols = min(nc, n - s["tile_n"] * nc)
+        assert 0 <= s["row"] < tile_rows and 0 <= s["col"] < tile_cols
+        assert 0 <= s["kstep"] < nk and 0 <= s["payload"] <= 30
+        k_ = (s["tile_m"], s["tile_n"], s["kstep"] // gi)
+        assert k_ not in key
+        key.add(k_)
