@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--skip-injection", action="store_true", help="do not run the injection-rate sweep")
     p.add_argument("--plain-only", action="store_true", help="time only the FT-off kernel (profiling)")
     p.add_argument("--ft-only", action="store_true", help="time only the FT kernel (profiling)")
+    p.add_argument("--probe", action="store_true",
+                   help="one FT launch, one plain launch and one 1 GiB elementwise copy, then exit "
+                        "(for hardware-counter runs: the copy calibrates FETCH_SIZE / WRITE_SIZE)")
     return p.parse_args()
 
 
@@ -131,6 +134,20 @@ def main():
     def call(level, report=None):
         return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, 1.0, dC.data_ptr(), m,
                             level, 0.0, sh, report)
+
+    if args.probe:
+        torch.cuda.synchronize()
+        call(F.FT_CORRECT)
+        torch.cuda.synchronize()
+        call(F.FT_OFF)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 28, device="cuda")        # 1 GiB read, 1 GiB written
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        F.ftgemm_destroy(h)
+        print(json.dumps({"probe": True, "copy_bytes": src.numel() * 4, "m": m, "n": n, "k": k}), flush=True)
+        return
 
     # a checked run first: the clean production path must raise no event
     rep = F.ReportBuffer(64)

@@ -29,6 +29,8 @@
 // The k index of the two lane halves is permuted (lane half h takes k = 8g +
 // 4h + s in MFMA s of group g) so the B operand is one 16-byte LDS read per
 // four MFMAs.
+#include <type_traits>
+
 #include "ftgemm_internal.h"
 
 namespace ftgemm_impl {
@@ -46,6 +48,7 @@ struct Smem {
     float Bs[2][BN][BK + 4];    // B panel, j-major (k contiguous), padded: conflict-free 16 B reads
     float wsum[2][BK];          // e^T A of the panel, per k
     float vsum[3][BK];          // B e of the panel, per k (accumulated across waves, 3 rotating slots)
+    float dummy[256];           // sink for the stores/atomics of lanes that own no value
     float rowpart[WN][BM];      // check: row sums per wave column
     float colpart[WM][BN];      // check: column sums per wave row
     float nsum[NW][2];          // check: per-wave sums of ||a_i||, ||b_j||
@@ -68,14 +71,15 @@ __device__ __forceinline__ float xor_reduce(float x) {
     return x;
 }
 
-// Reduce-scatter of N values over the 32 lanes of a wave half (lanes that
-// differ in bits 0..4).  Afterwards lane l holds, in x[0 .. max(N/32,1)),
-// the sums of original entries q + (N/32) * (l % 32) (N >= 32), or of entry
-// (l % 32) >> (5 - log2 N) (N < 32; neighbouring lanes hold copies).
-template <int N, int M>
-struct HalfReduceScatter {
+// Reduce-scatter of N values over the lanes that differ in the mask bits
+// M, M/2, ..., MLO (powers of two).  The first log2(N) masks halve the value
+// count, the rest reduce the single survivor, so afterwards x[0] of lane l
+// holds the sum of original entry ((l / (M >> (log2 N - 1))) mod N) over all
+// lanes equal to l outside those bits (for N = 1: the plain sum).
+template <int N, int M, int MLO = 1>
+struct ReduceScatter {
     __device__ __forceinline__ static void run(float* x, int lane) {
-        if constexpr (M >= 1) {
+        if constexpr (M >= MLO && M >= 1) {
             if constexpr (N > 1) {
                 const bool up = (lane & M) != 0;
 #pragma unroll
@@ -84,14 +88,20 @@ struct HalfReduceScatter {
                     const float keep = up ? x[q + N / 2] : x[q];
                     x[q] = keep + __shfl_xor(send, M);
                 }
-                HalfReduceScatter<N / 2, M / 2>::run(x, lane);
+                ReduceScatter<N / 2, M / 2, MLO>::run(x, lane);
             } else {
                 x[0] += __shfl_xor(x[0], M);
-                HalfReduceScatter<1, M / 2>::run(x, lane);
+                ReduceScatter<1, M / 2, MLO>::run(x, lane);
             }
         }
     }
 };
+
+// the 32 lanes of one wave half (bits 0..4)
+template <int N, int M>
+using HalfReduceScatter = ReduceScatter<N, M, 1>;
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 __device__ __forceinline__ float bitflip(float v, int bit) {
     return __uint_as_float(__float_as_uint(v) ^ (1u << (bit & 31)));
@@ -116,7 +126,10 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     constexpr int COL0 = SPLIT ? BM : 0;
     static_assert(MI >= 1 && NI >= 1 && NA >= 1 && NB >= 1 && BK % 8 == 0, "tile shape");
     static_assert(NT % (BM / 4) == 0 || (BM / 4) % 64 == 0, "A slot mapping");
-    static_assert(NT % BKQ == 0 && 64 % BKQ == 0, "B slot mapping");
+    static_assert(NT % BKQ == 0 && 64 % BKQ == 0 && BKQ <= 16, "B slot mapping");
+    static_assert(NA <= AG, "encode reduce-scatter needs NA <= AG");
+    constexpr int SG_VALU = FT > 0 ? 3 : 1;   // interleave pattern of the k-step
+    constexpr int SG_DS = FT > 0 ? 2 : 1;
 
     __shared__ Smem<BM, BN, BK, WM, WN> sm;
 
@@ -229,18 +242,17 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
         }
     };
 
-    // registers -> LDS, fused with the checksum encodings of the panel (Eq. 1-2)
+    // registers -> LDS, fused with the checksum encodings of the panel (Eq. 1-2).
+    // No lane-divergent branch, so it can interleave with the MFMA stream:
+    // lanes that own no result store into a private dummy slot instead.
     auto store_panels = [&](int buf, int vslot) {
+        float ws[NA];
 #pragma unroll
         for (int r = 0; r < NA; ++r) {
             const int f = tid + NT * r;
             const int i4 = f % (BM / 4), kk = f / (BM / 4);
             *reinterpret_cast<f32x4*>(&sm.As[buf][kk][4 * i4]) = ra[r];
-            if constexpr (FT > 0) {   // e^T A: the AG lanes holding column kk cover all BM rows
-                float s = (ra[r][0] + ra[r][1]) + (ra[r][2] + ra[r][3]);
-                s = xor_reduce<AG / 2>(s);
-                if ((lane & (AG - 1)) == 0) sm.wsum[buf][kk] = s;
-            }
+            ws[r] = (ra[r][0] + ra[r][1]) + (ra[r][2] + ra[r][3]);
         }
         f32x4 vp = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -248,18 +260,28 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
             const int f = tid + NT * r;
             const int kq = f % BKQ, jj = f / BKQ;
             *reinterpret_cast<f32x4*>(&sm.Bs[buf][jj][4 * kq]) = rb[r];
-            if constexpr (FT > 0) vp += rb[r];
+            vp += rb[r];
         }
-        if constexpr (FT > 0) {   // B e: lanes of one k-quad reduce in-wave, waves add in LDS
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int m = 32; m >= BKQ; m >>= 1) vp[q] += __shfl_xor(vp[q], m);
+        if constexpr (FT > 0) {
+            // e^T A: slot r's column kk is held by AG consecutive lanes; one
+            // reduce-scatter over those lanes leaves slot ((lane >> WSH) % NA)
+            // in every lane, written by the lanes whose low WSH bits are zero.
+            constexpr int WSH = ilog2(AG) - ilog2(NA);
+            ReduceScatter<NA, AG / 2, 1>::run(ws, lane);
+            {
+                const int r = (lane >> WSH) & (NA - 1);
+                const int kk = (tid - (lane & (AG - 1)) + NT * r) / (BM / 4);
+                float* dst = ((lane & ((1 << WSH) - 1)) == 0) ? &sm.wsum[buf][kk] : &sm.dummy[lane];
+                *dst = ws[0];
             }
-            if (lane < BKQ) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) atomicAdd(&sm.vsum[vslot][4 * lane + q], vp[q]);
-            }
+            // B e: the 4 k of k-quad (lane % BKQ) are summed over the lanes of
+            // that quad (bits log2(BKQ)..5); lane keeps k = 4 (lane % BKQ) +
+            // ((lane >> 4) & 3); waves then add their partials in LDS.
+            float vx[4] = {vp[0], vp[1], vp[2], vp[3]};
+            ReduceScatter<4, 32, BKQ>::run(vx, lane);
+            const int kv = 4 * (lane % BKQ) + ((lane >> 4) & 3);
+            float* dst = ((lane & (16 - BKQ)) == 0) ? &sm.vsum[vslot][kv] : &sm.dummy[lane];
+            atomicAdd(dst, vx[0]);
         }
     };
 
@@ -271,81 +293,106 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0.0f;
 
-    // owner-held checksum state: reference row checksum and ||a||^2 of my_row,
-    // reference column checksum and ||b||^2 of my_col
-    float Rr = 0.f, na2 = 0.f, Sc = 0.f, nb2 = 0.f;
+    // Owned checksum vectors.  With SPLIT, thread t < BM owns row t (reference
+    // row checksum R and ||a||^2) and the next BN threads own the columns
+    // (S and ||b||^2), one vector per thread; otherwise every thread owns row
+    // t (ck0, nq0) and column t (ck1, nq1), clamped in range and ignored when
+    // out of range.  Addresses are selected per thread so the update is free
+    // of branches and can be scheduled between MFMAs.
+    float ck0 = 0.f, nq0 = 0.f, ck1 = 0.f, nq1 = 0.f;
+    float& Rr = ck0;
+    float& na2 = nq0;
+    float& Sc = SPLIT ? ck0 : ck1;
+    float& nb2 = SPLIT ? nq0 : nq1;
+    const bool row_role = !SPLIT || tid < BM;
+    const int x0_stride = row_role ? BM : 1;
+    const int x0_off = row_role ? min(tid, BM - 1) : min(max(tid - COL0, 0), BN - 1) * (BK + 4);
+    const int x0_buf = row_role ? BK * BM : BN * (BK + 4);
+    const float* const x0_arr = row_role ? &sm.As[0][0][0] : &sm.Bs[0][0][0];
+    const int x1_row = min(tid, BN - 1);
 
-    load_panels(0);
-    store_panels(0, 0);
-    __syncthreads();
-
-    for (int t = 0; t < nk; ++t) {
-        const int cur = t & 1;
-        const int vcur = t % 3;
-        if (t + 1 < nk) load_panels(t + 1);
-        if constexpr (FT > 0) {   // slot for step t+2: its last reader finished before this step
-            const int vfree = (t + 2) % 3;
-            for (int x = tid; x < BK; x += NT) sm.vsum[vfree][x] = 0.f;
+    // one group of 8 k: 4 MFMA k-substeps on every block of the wave tile
+    auto mfma_group = [&](int cur, int g) {
+        f32x4 bf[NI];
+#pragma unroll
+        for (int bj = 0; bj < NI; ++bj)
+            bf[bj] = *reinterpret_cast<const f32x4*>(&sm.Bs[cur][wn * TN + 32 * bj + l32][8 * g + 4 * hh]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            float af[MI];
+#pragma unroll
+            for (int bi = 0; bi < MI; ++bi) af[bi] = sm.As[cur][8 * g + 4 * hh + s][wm * TM + 32 * bi + l32];
+#pragma unroll
+            for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NI; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(bf[bj][s], af[bi], acc[bi][bj], 0, 0, 0);
         }
+    };
 
-        // ---- MFMA main loop over the panel ----
+    // reference checksum update (Eq. 4) for the same 8 k:
+    //   R_i += sum_k A[i,k] (B e)[k],  S_j += sum_k (e^T A)[k] B[k,j],  plus the norms
+    auto ft_group = [&](int cur, int vcur, int g) {
+        const float* px = x0_arr + cur * x0_buf + x0_off + 8 * g * x0_stride;
+        const float* py = row_role ? &sm.vsum[vcur][8 * g] : &sm.wsum[cur][8 * g];
+        const f32x4 ya = *reinterpret_cast<const f32x4*>(py);
+        const f32x4 yb = *reinterpret_cast<const f32x4*>(py + 4);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float x = px[q * x0_stride];
+            ck0 = fmaf(x, q < 4 ? ya[q] : yb[q - 4], ck0);
+            nq0 = fmaf(x, x, nq0);
+        }
+        if constexpr (!SPLIT) {
+            const f32x4 b0 = *reinterpret_cast<const f32x4*>(&sm.Bs[cur][x1_row][8 * g]);
+            const f32x4 b1 = *reinterpret_cast<const f32x4*>(&sm.Bs[cur][x1_row][8 * g + 4]);
+            const f32x4 w0 = *reinterpret_cast<const f32x4*>(&sm.wsum[cur][8 * g]);
+            const f32x4 w1 = *reinterpret_cast<const f32x4*>(&sm.wsum[cur][8 * g + 4]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ck1 = fmaf(w0[q], b0[q], ck1);
+                nq1 = fmaf(b0[q], b0[q], nq1);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ck1 = fmaf(w1[q], b1[q], ck1);
+                nq1 = fmaf(b1[q], b1[q], nq1);
+            }
+        }
+    };
+
+    // One k-step.  The next panel's global loads are issued first; the LDS
+    // store and encode of that panel follow the last MFMA group (its loads
+    // have landed by then) and, like the checksum update, carry no branch,
+    // so the compiler can interleave them with the MFMAs in flight.
+    auto step = [&](int t, auto has_next) {
+        constexpr bool NEXT = decltype(has_next)::value;
+        const int cur = t & 1;
+        if constexpr (NEXT) load_panels(t + 1);
+        if constexpr (FT > 0 && NEXT)   // slot for step t+2: its last reader finished before this step
+            (&sm.vsum[(t + 2) % 3][0])[tid < BK ? tid : BK - 1] = 0.f;
 #pragma unroll
         for (int g = 0; g < BK / 8; ++g) {
-            f32x4 bf[NI];
-#pragma unroll
-            for (int bj = 0; bj < NI; ++bj)
-                bf[bj] = *reinterpret_cast<const f32x4*>(&sm.Bs[cur][wn * TN + 32 * bj + l32][8 * g + 4 * hh]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                float af[MI];
-#pragma unroll
-                for (int bi = 0; bi < MI; ++bi) af[bi] = sm.As[cur][8 * g + 4 * hh + s][wm * TM + 32 * bi + l32];
-#pragma unroll
-                for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < NI; ++bj)
-                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(bf[bj][s], af[bi], acc[bi][bj], 0, 0, 0);
+            mfma_group(cur, g);
+            if constexpr (FT > 0) ft_group(cur, t % 3, g);
+            if constexpr (NEXT) {
+                if (g == (BK / 8 >= 2 ? BK / 8 - 2 : 0)) store_panels(cur ^ 1, (t + 1) % 3);
             }
         }
-
-        // ---- reference checksum update (Eq. 4) ----
-        if constexpr (FT > 0) {
-            if (my_row >= 0) {
-                float rs = 0.f, q2 = 0.f;
+        // Interleave: after each MFMA issue up to SG_VALU vector ALU and SG_DS LDS
+        // instructions of the step (operand reads, checksum update, next-panel
+        // store and encode), which then execute while the MFMA is in flight.
+        constexpr int NMFMA = (BK / 2) * MI * NI;
 #pragma unroll
-                for (int k4 = 0; k4 < BK / 4; ++k4) {
-                    const f32x4 v = *reinterpret_cast<const f32x4*>(&sm.vsum[vcur][4 * k4]);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float x = sm.As[cur][4 * k4 + q][my_row];
-                        rs = fmaf(x, v[q], rs);
-                        q2 = fmaf(x, x, q2);
-                    }
-                }
-                Rr += rs;
-                na2 += q2;
-            }
-            if (my_col >= 0) {
-                float cs = 0.f, q2 = 0.f;
-#pragma unroll
-                for (int k4 = 0; k4 < BK / 4; ++k4) {
-                    const f32x4 b = *reinterpret_cast<const f32x4*>(&sm.Bs[cur][my_col][4 * k4]);
-                    const f32x4 w = *reinterpret_cast<const f32x4*>(&sm.wsum[cur][4 * k4]);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        cs = fmaf(w[q], b[q], cs);
-                        q2 = fmaf(b[q], b[q], q2);
-                    }
-                }
-                Sc += cs;
-                nb2 += q2;
-            }
+        for (int i = 0; i < NMFMA; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);        // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, SG_VALU, 0);  // VALU
+            __builtin_amdgcn_sched_group_barrier(0x080, SG_DS, 0);    // LDS
         }
+    };
 
-        // next panel to LDS now: its staging registers are free during the check
-        if (t + 1 < nk) store_panels(cur ^ 1, (t + 1) % 3);
-
-        // ---- injection hook: faults of this k-step hit the accumulator ----
+    // ---- injection hook: faults of k-step t hit the accumulator ----
+    auto inject = [&](int t) {
         if constexpr (INJ) {
             while (fnext < sm.nf && sm.fault[fnext].kstep == t) {
                 const ftgemm_fault_t f = sm.fault[fnext];
@@ -383,7 +430,9 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                 ++fnext;
             }
         }
+    };
 
+    auto check = [&](int t) {
         // ---- online check ----
         bool do_check = false;
         if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
@@ -571,8 +620,20 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                 }
             }
         }
+    };
+
+    load_panels(0);
+    store_panels(0, 0);
+    __syncthreads();
+    for (int t = 0; t + 1 < nk; ++t) {
+        step(t, std::true_type{});
+        inject(t);
+        check(t);
         __syncthreads();
     }
+    step(nk - 1, std::false_type{});
+    inject(nk - 1);
+    check(nk - 1);
 
     // ---- epilogue: C = alpha * P + beta * C ----
 #pragma unroll
