@@ -51,7 +51,7 @@ struct Smem {
     float dummy[256];           // sink for the stores/atomics of lanes that own no value
     float rowpart[WN][BM];      // check: row sums per wave column
     float colpart[WM][BN];      // check: column sums per wave row
-    float nsum[NW][2];          // check: per-wave sums of ||a_i||, ||b_j||
+    float nsum[2][NW];          // check: per-wave sums of ||a_i|| and of ||b_j||
     int census[NW][4];          // check: per-wave (#rows, first row, #cols, first col)
     float excl[WN];             // correction: row sum without the faulty element
     float bc[8];                // broadcast scratch
@@ -63,45 +63,66 @@ struct Smem {
 // ---------------------------------------------------------------------------
 // cross-lane helpers (wave64)
 // ---------------------------------------------------------------------------
-template <int MASK_MAX>
-__device__ __forceinline__ float xor_reduce(float x) {
-    // sum over lanes differing only in bits of MASK_MAX..1
-#pragma unroll
-    for (int m = MASK_MAX; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-    return x;
+// Partner value for the exchange level on lane bit BIT.  Levels 0-3 stay
+// inside a 16-lane row and use DPP (no LDS round trip): quad_perm [1,0,3,2]
+// (partner l^1), quad_perm [3,2,1,0] (l^3), row_half_mirror (l^7 within 8)
+// and row_ror:8 (l^8); level 4 is an LDS swizzle (l^16), level 5 a
+// permute (l^32).  Each pairs lane l with a lane whose bit BIT differs and
+// whose higher bits agree, which is all a butterfly reduction needs: the
+// sets of lanes summed into each value stay disjoint and end up complete.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
 
-// Reduce-scatter of N values over the lanes that differ in the mask bits
-// M, M/2, ..., MLO (powers of two).  The first log2(N) masks halve the value
-// count, the rest reduce the single survivor, so afterwards x[0] of lane l
-// holds the sum of original entry ((l / (M >> (log2 N - 1))) mod N) over all
-// lanes equal to l outside those bits (for N = 1: the plain sum).
-template <int N, int M, int MLO = 1>
+template <int BIT>
+__device__ __forceinline__ float partner(float x) {
+    if constexpr (BIT == 0) return dpp_mov<0xB1>(x);        // quad_perm [1,0,3,2]
+    else if constexpr (BIT == 1) return dpp_mov<0x1B>(x);   // quad_perm [3,2,1,0]
+    else if constexpr (BIT == 2) return dpp_mov<0x141>(x);  // row_half_mirror
+    else if constexpr (BIT == 3) return dpp_mov<0x128>(x);  // row_ror:8
+    else if constexpr (BIT == 4)                            // swizzle: swap 16-lane halves of 32
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
+    else return __shfl_xor(x, 32);
+}
+
+// Reduce-scatter of N values over the lanes that differ only in lane bits
+// BIT, BIT-1, ..., BLO.  The first log2(N) levels halve the value count, the
+// rest reduce the single survivor.  Afterwards x[0] of lane l holds the sum,
+// over all those lanes, of original entry sum_b bit_b(l) * (N_b / 2), where
+// N_b is the count entering the halving level on bit b (for N = 1: the plain
+// sum).  Example: N = 16 over bits 4..0 leaves entry (l >> 1) & 15.
+template <int N, int BIT, int BLO = 0>
 struct ReduceScatter {
     __device__ __forceinline__ static void run(float* x, int lane) {
-        if constexpr (M >= MLO && M >= 1) {
+        if constexpr (BIT >= BLO && BIT >= 0) {
             if constexpr (N > 1) {
-                const bool up = (lane & M) != 0;
+                const bool up = ((lane >> BIT) & 1) != 0;
 #pragma unroll
                 for (int q = 0; q < N / 2; ++q) {
                     const float send = up ? x[q] : x[q + N / 2];
                     const float keep = up ? x[q + N / 2] : x[q];
-                    x[q] = keep + __shfl_xor(send, M);
+                    x[q] = keep + partner<BIT>(send);
                 }
-                ReduceScatter<N / 2, M / 2, MLO>::run(x, lane);
+                ReduceScatter<N / 2, BIT - 1, BLO>::run(x, lane);
             } else {
-                x[0] += __shfl_xor(x[0], M);
-                ReduceScatter<1, M / 2, MLO>::run(x, lane);
+                x[0] += partner<BIT>(x[0]);
+                ReduceScatter<1, BIT - 1, BLO>::run(x, lane);
             }
         }
     }
 };
 
-// the 32 lanes of one wave half (bits 0..4)
-template <int N, int M>
-using HalfReduceScatter = ReduceScatter<N, M, 1>;
-
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Sum over the 64 lanes of a wave, returned as a wave-uniform value.
+__device__ __forceinline__ float wave_sum(float x) {
+    float v[1] = {x};
+    ReduceScatter<1, 4, 0>::run(v, 0);
+    const int lo = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 0);
+    const int hi = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 32);
+    return __builtin_bit_cast(float, lo) + __builtin_bit_cast(float, hi);
+}
 
 __device__ __forceinline__ float bitflip(float v, int bit) {
     return __uint_as_float(__float_as_uint(v) ^ (1u << (bit & 31)));
@@ -128,8 +149,6 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     static_assert(NT % (BM / 4) == 0 || (BM / 4) % 64 == 0, "A slot mapping");
     static_assert(NT % BKQ == 0 && 64 % BKQ == 0 && BKQ <= 16, "B slot mapping");
     static_assert(NA <= AG, "encode reduce-scatter needs NA <= AG");
-    constexpr int SG_VALU = FT > 0 ? 3 : 1;   // interleave pattern of the k-step
-    constexpr int SG_DS = FT > 0 ? 2 : 1;
 
     __shared__ Smem<BM, BN, BK, WM, WN> sm;
 
@@ -137,8 +156,12 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int l32 = lane & 31, hh = lane >> 5;
-    const int my_row = tid < BM ? tid : -1;
-    const int my_col = (tid >= COL0 && tid < COL0 + BN) ? tid - COL0 : -1;
+    // with SPLIT the first BM/64 wavefronts own rows and the next BN/64 own
+    // columns, so the role is wave-uniform (kept in scalar registers)
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const bool row_role = !SPLIT || wave_u < BM / 64;
+    const int my_row = (row_role && tid < BM) ? tid : -1;
+    const int my_col = SPLIT ? ((!row_role && tid < COL0 + BN) ? tid - COL0 : -1) : (tid < BN ? tid : -1);
 
     const int ntm = (a.M + BM - 1) / BM;
     const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
@@ -267,7 +290,7 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
             // reduce-scatter over those lanes leaves slot ((lane >> WSH) % NA)
             // in every lane, written by the lanes whose low WSH bits are zero.
             constexpr int WSH = ilog2(AG) - ilog2(NA);
-            ReduceScatter<NA, AG / 2, 1>::run(ws, lane);
+            ReduceScatter<NA, ilog2(AG) - 1, 0>::run(ws, lane);
             {
                 const int r = (lane >> WSH) & (NA - 1);
                 const int kk = (tid - (lane & (AG - 1)) + NT * r) / (BM / 4);
@@ -278,7 +301,7 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
             // that quad (bits log2(BKQ)..5); lane keeps k = 4 (lane % BKQ) +
             // ((lane >> 4) & 3); waves then add their partials in LDS.
             float vx[4] = {vp[0], vp[1], vp[2], vp[3]};
-            ReduceScatter<4, 32, BKQ>::run(vx, lane);
+            ReduceScatter<4, 5, ilog2(BKQ)>::run(vx, lane);
             const int kv = 4 * (lane % BKQ) + ((lane >> 4) & 3);
             float* dst = ((lane & (16 - BKQ)) == 0) ? &sm.vsum[vslot][kv] : &sm.dummy[lane];
             atomicAdd(dst, vx[0]);
@@ -304,7 +327,6 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     float& na2 = nq0;
     float& Sc = SPLIT ? ck0 : ck1;
     float& nb2 = SPLIT ? nq0 : nq1;
-    const bool row_role = !SPLIT || tid < BM;
     const int x0_stride = row_role ? BM : 1;
     const int x0_off = row_role ? min(tid, BM - 1) : min(max(tid - COL0, 0), BN - 1) * (BK + 4);
     const int x0_buf = row_role ? BK * BM : BN * (BK + 4);
@@ -379,52 +401,45 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                 if (g == (BK / 8 >= 2 ? BK / 8 - 2 : 0)) store_panels(cur ^ 1, (t + 1) % 3);
             }
         }
-        // Interleave: after each MFMA issue up to SG_VALU vector ALU and SG_DS LDS
-        // instructions of the step (operand reads, checksum update, next-panel
-        // store and encode), which then execute while the MFMA is in flight.
-        constexpr int NMFMA = (BK / 2) * MI * NI;
-#pragma unroll
-        for (int i = 0; i < NMFMA; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);        // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, SG_VALU, 0);  // VALU
-            __builtin_amdgcn_sched_group_barrier(0x080, SG_DS, 0);    // LDS
-        }
     };
 
     // ---- injection hook: faults of k-step t hit the accumulator ----
     auto inject = [&](int t) {
         if constexpr (INJ) {
-            while (fnext < sm.nf && sm.fault[fnext].kstep == t) {
+            while (fnext < sm.nf && sm.fault[fnext].kstep == t) {   // uniform loop
                 const ftgemm_fault_t f = sm.fault[fnext];
-                if (f.row / TM == wm && f.col / TN == wn) {
-                    const int ir = f.row % TM, jr = f.col % TN;
-                    const int fbi = ir / 32, fbj = jr / 32, jj = jr % 32;
-                    const int fh = (jj >> 2) & 1, fr = ((jj >> 3) << 2) | (jj & 3);
-                    if (lane == fh * 32 + (ir % 32)) {
-                        float oldv = 0.f, newv = 0.f;
+                const int ir = f.row % TM, jr = f.col % TN;
+                const int fbi = ir / 32, fbj = jr / 32, jj = jr % 32;
+                const int freg = ((jj >> 3) << 2) | (jj & 3);
+                const bool own = f.row / TM == wm && f.col / TN == wn && lane == ((jj >> 2) & 1) * 32 + (ir % 32);
+                float oldv = 0.f, newv = 0.f;
 #pragma unroll
-                        for (int bi = 0; bi < MI; ++bi)
+                for (int bi = 0; bi < MI; ++bi)
 #pragma unroll
-                            for (int bj = 0; bj < NI; ++bj)
+                    for (int bj = 0; bj < NI; ++bj) {
+                        if (bi == fbi && bj == fbj) {
 #pragma unroll
-                                for (int r = 0; r < 16; ++r)
-                                    if (bi == fbi && bj == fbj && r == fr) {
-                                        oldv = acc[bi][bj][r];
-                                        newv = (f.kind == FTGEMM_FAULT_XOR) ? bitflip(oldv, (int)f.payload)
-                                                                            : oldv + f.payload;
-                                        acc[bi][bj][r] = newv;
-                                    }
-                        const int slot = (int)atomicAdd(&a.counters[CNT_FAULTS], 1u);
-                        sm.fslot[fnext] = slot;
-                        if (slot < a.fault_log_cap) {
-                            ftgemm_fault_log_t L;
-                            L.problem = a.problem; L.tile_m = tm; L.tile_n = tn; L.kstep = t;
-                            L.row = f.row; L.col = f.col; L.kind = f.kind; L.check_step = -1;
-                            L.old_v = oldv; L.new_v = newv;
-                            L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
-                            L.pad0_ = L.pad1_ = 0.f;
-                            a.fault_log[slot] = L;
+                            for (int r = 0; r < 16; ++r) {
+                                const float x = acc[bi][bj][r];
+                                const bool hit = own && r == freg;
+                                const float y = (f.kind == FTGEMM_FAULT_XOR) ? bitflip(x, (int)f.payload) : x + f.payload;
+                                oldv = hit ? x : oldv;
+                                newv = hit ? y : newv;
+                                acc[bi][bj][r] = hit ? y : x;
+                            }
                         }
+                    }
+                if (own) {
+                    const int slot = (int)atomicAdd(&a.counters[CNT_FAULTS], 1u);
+                    sm.fslot[fnext] = slot;
+                    if (slot < a.fault_log_cap) {
+                        ftgemm_fault_log_t L;
+                        L.problem = a.problem; L.tile_m = tm; L.tile_n = tn; L.kstep = t;
+                        L.row = f.row; L.col = f.col; L.kind = f.kind; L.check_step = -1;
+                        L.old_v = oldv; L.new_v = newv;
+                        L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
+                        L.pad0_ = L.pad1_ = 0.f;
+                        a.fault_log[slot] = L;
                     }
                 }
                 ++fnext;
@@ -432,7 +447,7 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
         }
     };
 
-    auto check = [&](int t) {
+    auto check = [&](int t) -> bool {
         // ---- online check ----
         bool do_check = false;
         if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
@@ -463,7 +478,7 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                     }
                     rpart[bi] += rs;
                 }
-                HalfReduceScatter<16, 16>::run(cs, lane);
+                ReduceScatter<16, 4, 0>::run(cs, lane);
                 if ((l32 & 1) == 0) {
                     const int r = l32 >> 1;
                     sm.colpart[wm][wn * TN + 32 * bj + 8 * (r >> 2) + 4 * hh + (r & 3)] = cs[0];
@@ -478,14 +493,14 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
             // (2) per-wave sums of the row and column norms for the threshold
             const float na = (my_row >= 0) ? sqrtf(na2) : 0.f;
             const float nb = (my_col >= 0) ? sqrtf(nb2) : 0.f;
-            const float wna = xor_reduce<32>(na), wnb = xor_reduce<32>(nb);
-            if (lane == 0) { sm.nsum[wave][0] = wna; sm.nsum[wave][1] = wnb; }
+            const float wna = wave_sum(na), wnb = wave_sum(nb);
+            if (lane == 0) { sm.nsum[0][wave] = wna; sm.nsum[1][wave] = wnb; }
             __syncthreads();
 
             // (3) residuals, thresholds, flags
             float sa = 0.f, sb = 0.f;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) { sa += sm.nsum[w][0]; sb += sm.nsum[w][1]; }
+            for (int w = 0; w < NW; ++w) { sa += sm.nsum[0][w]; sb += sm.nsum[1][w]; }
             const int kp = min((t + 1) * BK, a.K);
             const float base = a.tol_c * 2.0f * kUnitRoundoff;
             float rres = 0.f, cres = 0.f, taur = 0.f, tauc = 0.f;
@@ -539,46 +554,55 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                 const bool correct = (FT == 2) && nr == 1 && ncl == 1;
                 if (my_row >= 0 && my_row == fr) { sm.bc[0] = Rr; sm.bc[1] = rres; sm.bc[2] = taur; }
                 if (my_col >= 0 && my_col == fc) { sm.bc[3] = cres; sm.bc[4] = tauc; }
-                bool own = false;
+                // Coordinates of (fr, fc) in the accumulator layout; all but the
+                // lane tests are uniform, so the block is picked by scalar
+                // branches and the element by per-lane selects (compact code).
+                const int fbi = correct ? (fr % TM) / 32 : -1;
+                const int fjr = correct ? fc % TN : 0;
+                const int fbj = fjr / 32, fjj = fjr % 32;
+                const int freg = ((fjj >> 3) << 2) | (fjj & 3);
+                const bool row_lane = correct && wm == fr / TM && l32 == (fr & 31);
+                const bool own = row_lane && wn == fc / TN && hh == ((fjj >> 2) & 1);
                 float oldv = 0.f;
                 if (correct && wm == fr / TM) {
-                    // partial sum of row fr over this wave's columns, without (fr, fc)
-                    const int fbi = (fr % TM) / 32;
+                    // sum of row fr over this wave's columns, without element (fr, fc)
                     float part = 0.f;
-                    if (l32 == (fr & 31)) {
 #pragma unroll
-                        for (int bi = 0; bi < MI; ++bi)
+                    for (int bi = 0; bi < MI; ++bi) {
+                        if (bi == fbi) {
 #pragma unroll
                             for (int bj = 0; bj < NI; ++bj)
 #pragma unroll
                                 for (int r = 0; r < 16; ++r) {
-                                    const int j = wn * TN + 32 * bj + 8 * (r >> 2) + 4 * hh + (r & 3);
-                                    if (bi == fbi) {
-                                        if (j == fc) { own = true; oldv = acc[bi][bj][r]; }
-                                        else part += acc[bi][bj][r];
-                                    }
+                                    const float x = acc[bi][bj][r];
+                                    const bool hit = own && bj == fbj && r == freg;
+                                    part += hit ? 0.f : x;
+                                    oldv = hit ? x : oldv;
                                 }
+                        }
                     }
+                    part = row_lane ? part : 0.f;
                     part += __shfl_xor(part, 32);
-                    if (lane == (fr & 31)) sm.excl[wn] = part;
+                    float* dst = (lane == (fr & 31)) ? &sm.excl[wn] : &sm.dummy[lane];
+                    *dst = part;
                 }
                 __syncthreads();
                 if (correct) {
+                    float excl = 0.f;
+#pragma unroll
+                    for (int w = 0; w < WN; ++w) excl += sm.excl[w];
+                    const float newv = sm.bc[0] - excl;
+#pragma unroll
+                    for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < NI; ++bj) {
+                            if (bi == fbi && bj == fbj) {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r)
+                                    acc[bi][bj][r] = (own && r == freg) ? newv : acc[bi][bj][r];
+                            }
+                        }
                     if (own) {
-                        float excl = 0.f;
-#pragma unroll
-                        for (int w = 0; w < WN; ++w) excl += sm.excl[w];
-                        const float newv = sm.bc[0] - excl;
-                        const int fbi = (fr % TM) / 32;
-#pragma unroll
-                        for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-                            for (int bj = 0; bj < NI; ++bj)
-#pragma unroll
-                                for (int r = 0; r < 16; ++r) {
-                                    const int j = wn * TN + 32 * bj + 8 * (r >> 2) + 4 * hh + (r & 3);
-                                    if (bi == fbi && j == fc) acc[bi][bj][r] = newv;
-                                }
                         const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
                         atomicAdd(&a.counters[CNT_DETECTED], 1u);
                         atomicAdd(&a.counters[CNT_CORRECTED], 1u);
@@ -620,6 +644,7 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
                 }
             }
         }
+        return do_check;
     };
 
     load_panels(0);
@@ -628,8 +653,9 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     for (int t = 0; t + 1 < nk; ++t) {
         step(t, std::true_type{});
         inject(t);
-        check(t);
-        __syncthreads();
+        // a check ends with a workgroup barrier after its census, which also
+        // orders this step's LDS panel writes before the next step's reads
+        if (!check(t)) __syncthreads();
     }
     step(nk - 1, std::false_type{});
     inject(nk - 1);
