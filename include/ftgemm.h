@@ -124,13 +124,19 @@ typedef struct {
 } ftgemm_report_t;
 
 /* Create a handle on `device` for operands of type `dtype`.  Allocates the
- * device event log and counters.  Returns FTGEMM_UNSUPPORTED if the device is
- * not gfx950. */
+ * device event log and counters.  FTGEMM_F32: A, B are float.  FTGEMM_BF16:
+ * A, B are bfloat16 codes (uint16, same column-major layout); products and
+ * accumulation are FP32, checksums and the check run in FP32 on the exactly
+ * decoded values (section 4.2.3).  Returns FTGEMM_UNSUPPORTED for a dtype
+ * with no compiled kernel or a device that is not gfx950. */
 int ftgemm_create(ftgemm_t* handle, int dtype, int device);
 int ftgemm_destroy(ftgemm_t handle);
 
 /* Per-tensor dequantisation scales for BF16/FP8 operands (default 1):
- * the product is computed as (scale_a * A) (scale_b * B). */
+ * the product is computed as (scale_a * A) (scale_b * B).  The scales are
+ * applied in the epilogue as alpha * scale_a * scale_b, after the checks,
+ * so powers of two keep the result bit-identical to scaling the operands.
+ * Ignored for FP32.  Returns FTGEMM_INVALID unless both are > 0. */
 int ftgemm_set_scales(ftgemm_t handle, float scale_a, float scale_b);
 
 /* Force a kernel configuration for later calls (NULL: automatic selection).

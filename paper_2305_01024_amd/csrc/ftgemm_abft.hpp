@@ -1,0 +1,470 @@
+// ftgemm_abft.hpp -- device code shared by every FT-GEMM kernel variant of
+// the library: lane-exchange helpers, the per-thread tile geometry, the online
+// check with locate/correct (section 2.2 Eq. 4, section 4.2.1, section 5.3),
+// the compile-time fault-injection hook and the epilogue.
+//
+// All of it works on the FP32 accumulator of 32 x 32 MFMA blocks, which has
+// the same lane layout for the FP32, BF16 and FP8 MFMA instructions: lane l
+// holds column (l % 32) of a block and rows 8 (r / 4) + 4 (l / 32) + (r % 4)
+// in register r.  The kernels compute the transposed tile P^T = B^T A^T, so a
+// block's "column" is a row i of C and its "rows" are columns j of C.
+#pragma once
+
+#include <type_traits>
+
+#include "ftgemm_internal.h"
+
+namespace ftgemm_impl {
+namespace abft {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kUnitRoundoff = 5.9604644775390625e-08f;  // 2^-24, binary32
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// ---------------------------------------------------------------------------
+// lane exchanges (wave64)
+// ---------------------------------------------------------------------------
+// Partner value for the exchange level on lane bit BIT.  Levels 0-3 stay
+// inside a 16-lane row and use DPP (no LDS round trip): quad_perm [1,0,3,2]
+// (partner l^1), quad_perm [3,2,1,0] (l^3), row_half_mirror (l^7 within 8)
+// and row_ror:8 (l^8); level 4 is an LDS swizzle (l^16), level 5 a permute
+// (l^32).  Each pairs lane l with a lane whose bit BIT differs and whose
+// higher bits agree, which is all a butterfly reduction needs: the sets of
+// lanes summed into each value stay disjoint and end up complete.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+template <int BIT>
+__device__ __forceinline__ float partner(float x) {
+    if constexpr (BIT == 0) return dpp_mov<0xB1>(x);        // quad_perm [1,0,3,2]
+    else if constexpr (BIT == 1) return dpp_mov<0x1B>(x);   // quad_perm [3,2,1,0]
+    else if constexpr (BIT == 2) return dpp_mov<0x141>(x);  // row_half_mirror
+    else if constexpr (BIT == 3) return dpp_mov<0x128>(x);  // row_ror:8
+    else if constexpr (BIT == 4)                            // swizzle: swap 16-lane halves of 32
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
+    else return __shfl_xor(x, 32);
+}
+
+// Reduce-scatter of N values over the lanes that differ only in lane bits
+// BIT, BIT-1, ..., BLO.  The first log2(N) levels halve the value count, the
+// rest reduce the single survivor.  Afterwards x[0] of lane l holds the sum,
+// over all those lanes, of original entry sum_b bit_b(l) * (N_b / 2), where
+// N_b is the count entering the halving level on bit b (for N = 1: the plain
+// sum).  Example: N = 16 over bits 4..0 leaves entry (l >> 1) & 15.
+template <int N, int BIT, int BLO = 0>
+struct ReduceScatter {
+    __device__ __forceinline__ static void run(float* x, int lane) {
+        if constexpr (BIT >= BLO && BIT >= 0) {
+            if constexpr (N > 1) {
+                const bool up = ((lane >> BIT) & 1) != 0;
+#pragma unroll
+                for (int q = 0; q < N / 2; ++q) {
+                    const float send = up ? x[q] : x[q + N / 2];
+                    const float keep = up ? x[q + N / 2] : x[q];
+                    x[q] = keep + partner<BIT>(send);
+                }
+                ReduceScatter<N / 2, BIT - 1, BLO>::run(x, lane);
+            } else {
+                x[0] += partner<BIT>(x[0]);
+                ReduceScatter<1, BIT - 1, BLO>::run(x, lane);
+            }
+        }
+    }
+};
+
+// Sum over the 64 lanes of a wave, returned as a wave-uniform value.
+__device__ __forceinline__ float wave_sum(float x) {
+    float v[1] = {x};
+    ReduceScatter<1, 4, 0>::run(v, 0);
+    const int lo = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 0);
+    const int hi = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 32);
+    return __builtin_bit_cast(float, lo) + __builtin_bit_cast(float, hi);
+}
+
+__device__ __forceinline__ float bitflip(float v, int bit) {
+    return __uint_as_float(__float_as_uint(v) ^ (1u << (bit & 31)));
+}
+
+// ---------------------------------------------------------------------------
+// tile geometry and per-thread roles
+// ---------------------------------------------------------------------------
+// A workgroup of WM x WN wavefronts computes one BM x BN tile (the check
+// tile); wavefront (wm, wn) holds the TM x TN sub-tile as MI x NI blocks.
+// Checksum owners: thread t < BM owns tile row t; the column owners are the
+// next BN threads when there are at least BM + BN threads (SPLIT), else
+// thread t < BN.  With SPLIT the role is wave-uniform.
+template <int BM_, int BN_, int WM_, int WN_>
+struct Geometry {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+    static constexpr int NT = 64 * WM * WN, NW = WM * WN;
+    static constexpr int TM = BM / WM, TN = BN / WN;
+    static constexpr int MI = TM / 32, NI = TN / 32;
+    static constexpr bool SPLIT = NT >= BM + BN;
+    static constexpr int COL0 = SPLIT ? BM : 0;
+    static_assert(MI >= 1 && NI >= 1, "each wavefront needs at least one 32 x 32 block");
+    static_assert(!SPLIT || BM % 64 == 0, "row owners must fill whole wavefronts");
+};
+
+struct Thread {
+    int tid, lane, wave, wm, wn, l32, hh;
+    bool row_role;
+    int my_row, my_col;     // owned tile row / column, -1 if none
+    int tm, tn, i0, j0, mI, nJ;
+};
+
+template <class G>
+__device__ __forceinline__ Thread make_thread(const LaunchArgs& a, int tm, int tn) {
+    Thread t;
+    t.tid = threadIdx.x;
+    t.lane = t.tid & 63;
+    t.wave = t.tid >> 6;
+    t.wm = t.wave % G::WM;
+    t.wn = t.wave / G::WM;
+    t.l32 = t.lane & 31;
+    t.hh = t.lane >> 5;
+    const int wave_u = __builtin_amdgcn_readfirstlane(t.wave);
+    t.row_role = !G::SPLIT || wave_u < G::BM / 64;
+    t.my_row = (t.row_role && t.tid < G::BM) ? t.tid : -1;
+    t.my_col = G::SPLIT ? ((!t.row_role && t.tid < G::COL0 + G::BN) ? t.tid - G::COL0 : -1)
+                        : (t.tid < G::BN ? t.tid : -1);
+    t.tm = tm;
+    t.tn = tn;
+    t.i0 = tm * G::BM;
+    t.j0 = tn * G::BN;
+    t.mI = min(G::BM, a.M - t.i0);
+    t.nJ = min(G::BN, a.N - t.j0);
+    return t;
+}
+
+// LDS scratch of the check and the injection hook
+template <class G>
+struct CheckLds {
+    float rowpart[G::WN][G::BM];    // row sums per wave column
+    float colpart[G::WM][G::BN];    // column sums per wave row
+    float nsum[2][G::NW];           // per-wave sums of ||a_i|| and of ||b_j||
+    int census[G::NW][4];           // per-wave (#rows, first row, #cols, first col)
+    float excl[G::WN];              // correction: row sum without the faulty element
+    float bc[8];                    // broadcast scratch
+    float dummy[64];                // sink for stores of lanes that own no value
+    ftgemm_fault_t fault[kMaxFaultsPerTile];
+    int fslot[kMaxFaultsPerTile];
+    int nf;
+};
+
+template <class G>
+using Acc = f32x16[G::MI][G::NI];
+
+// ---------------------------------------------------------------------------
+// fault injection hook (compiled only into INJ kernels)
+// ---------------------------------------------------------------------------
+// Collect this tile's fault sites into LDS, ordered by (kstep, row, col).
+template <class G>
+__device__ void gather_faults(CheckLds<G>& s, const LaunchArgs& a, const Thread& th) {
+    if (th.tid == 0) s.nf = 0;
+    __syncthreads();
+    for (int q = th.tid; q < a.n_faults; q += G::NT) {
+        const ftgemm_fault_t f = a.faults[q];
+        if (f.problem == a.problem && f.tile_m == th.tm && f.tile_n == th.tn) {
+            const int x = atomicAdd(&s.nf, 1);
+            if (x < kMaxFaultsPerTile) { s.fault[x] = f; s.fslot[x] = -1; }
+        }
+    }
+    __syncthreads();
+    if (th.tid == 0) {
+        const int n = min(s.nf, kMaxFaultsPerTile);
+        s.nf = n;
+        for (int x = 1; x < n; ++x) {
+            const ftgemm_fault_t f = s.fault[x];
+            int y = x - 1;
+            while (y >= 0 && (s.fault[y].kstep > f.kstep ||
+                              (s.fault[y].kstep == f.kstep && (s.fault[y].row > f.row ||
+                               (s.fault[y].row == f.row && s.fault[y].col > f.col))))) {
+                s.fault[y + 1] = s.fault[y];
+                --y;
+            }
+            s.fault[y + 1] = f;
+        }
+    }
+}
+
+// Faults of k-step t hit the accumulator (after that step's update): the
+// element is found with uniform block branches and per-lane selects.
+template <class G>
+__device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th,
+                                       int t, int& fnext) {
+    while (fnext < s.nf && s.fault[fnext].kstep == t) {
+        const ftgemm_fault_t f = s.fault[fnext];
+        const int ir = f.row % G::TM, jr = f.col % G::TN;
+        const int fbi = ir / 32, fbj = jr / 32, jj = jr % 32;
+        const int freg = ((jj >> 3) << 2) | (jj & 3);
+        const bool own = f.row / G::TM == th.wm && f.col / G::TN == th.wn &&
+                         th.lane == ((jj >> 2) & 1) * 32 + (ir % 32);
+        float oldv = 0.f, newv = 0.f;
+#pragma unroll
+        for (int bi = 0; bi < G::MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < G::NI; ++bj) {
+                if (bi == fbi && bj == fbj) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float x = acc[bi][bj][r];
+                        const bool hit = own && r == freg;
+                        const float y = (f.kind == FTGEMM_FAULT_XOR) ? bitflip(x, (int)f.payload) : x + f.payload;
+                        oldv = hit ? x : oldv;
+                        newv = hit ? y : newv;
+                        acc[bi][bj][r] = hit ? y : x;
+                    }
+                }
+            }
+        if (own) {
+            const int slot = (int)atomicAdd(&a.counters[CNT_FAULTS], 1u);
+            s.fslot[fnext] = slot;
+            if (slot < a.fault_log_cap) {
+                ftgemm_fault_log_t L;
+                L.problem = a.problem; L.tile_m = th.tm; L.tile_n = th.tn; L.kstep = t;
+                L.row = f.row; L.col = f.col; L.kind = f.kind; L.check_step = -1;
+                L.old_v = oldv; L.new_v = newv;
+                L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
+                L.pad0_ = L.pad1_ = 0.f;
+                a.fault_log[slot] = L;
+            }
+        }
+        ++fnext;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// online check (section 2.2: compare sums with the checksums against a
+// threshold; section 4.2.1: locate at the row/column intersection and
+// correct from the checksum)
+// ---------------------------------------------------------------------------
+// kp = number of k indices accumulated so far.  Rr/na2 are the owner's row
+// checksum and ||a||^2, Sc/nb2 the column ones (the same variables may alias
+// under SPLIT, where a thread owns only one of them).  Ends with a workgroup
+// barrier after the census (callers use it as the end-of-step barrier).
+template <class G, int FT, bool INJ>
+__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
+                      float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
+    constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
+    const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
+
+    // (1) one pass over the accumulator, one 32-column block at a time:
+    // per-lane partial row sums (over the lane's columns) and the block's
+    // column sums over this wave's rows; the 16 column sums of a lane are
+    // reduce-scattered over the 32 lanes of its half, leaving lane pair
+    // (2x, 2x+1) with entry x.
+    float rpart[MI];
+#pragma unroll
+    for (int bi = 0; bi < MI; ++bi) rpart[bi] = 0.f;
+#pragma unroll
+    for (int bj = 0; bj < NI; ++bj) {
+        float cs[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cs[r] = 0.f;
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi) {
+            float rs = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float x = acc[bi][bj][r];
+                cs[r] += x;
+                rs += x;
+            }
+            rpart[bi] += rs;
+        }
+        ReduceScatter<16, 4, 0>::run(cs, lane);
+        if ((l32 & 1) == 0) {
+            const int r = l32 >> 1;
+            s.colpart[wm][wn * TN + 32 * bj + 8 * (r >> 2) + 4 * hh + (r & 3)] = cs[0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < MI; ++bi) {
+        const float rs = rpart[bi] + __shfl_xor(rpart[bi], 32);
+        if (hh == 0) s.rowpart[wn][wm * TM + 32 * bi + l32] = rs;
+    }
+    // (2) per-wave sums of the row and column norms for the threshold
+    const float na = (th.my_row >= 0) ? sqrtf(na2) : 0.f;
+    const float nb = (th.my_col >= 0) ? sqrtf(nb2) : 0.f;
+    const float wna = wave_sum(na), wnb = wave_sum(nb);
+    if (lane == 0) { s.nsum[0][th.wave] = wna; s.nsum[1][th.wave] = wnb; }
+    __syncthreads();
+
+    // (3) residuals, thresholds (the analytic FP32 roundoff bound), flags
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) { sa += s.nsum[0][w]; sb += s.nsum[1][w]; }
+    const float base = a.tol_c * 2.0f * kUnitRoundoff;
+    float rres = 0.f, cres = 0.f, taur = 0.f, tauc = 0.f;
+    bool rf = false, cf = false;
+    if (th.my_row >= 0 && th.my_row < th.mI) {
+        float x = 0.f;
+#pragma unroll
+        for (int w = 0; w < WN; ++w) x += s.rowpart[w][th.my_row];
+        rres = x - Rr;
+        taur = base * (float)(kp + th.nJ + 1) * na * sb;
+        rf = !(fabsf(rres) <= taur);
+    }
+    if (th.my_col >= 0 && th.my_col < th.nJ) {
+        float x = 0.f;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) x += s.colpart[w][th.my_col];
+        cres = x - Sc;
+        tauc = base * (float)(kp + th.mI + 1) * nb * sa;
+        cf = !(fabsf(cres) <= tauc);
+    }
+    const unsigned long long rb = __ballot(rf), cb = __ballot(cf);
+    if (lane == 0) {
+        s.census[th.wave][0] = __popcll(rb);
+        s.census[th.wave][1] = rb ? th.wave * 64 + __ffsll((long long)rb) - 1 : -1;
+        s.census[th.wave][2] = __popcll(cb);
+        s.census[th.wave][3] = cb ? th.wave * 64 + __ffsll((long long)cb) - 1 - G::COL0 : -1;
+    }
+    if constexpr (INJ) {   // complete the fault log entries this check is the first to see
+        for (int q = flogged; q < fnext; ++q) {
+            const int slot = s.fslot[q];
+            if (slot < 0 || slot >= a.fault_log_cap) continue;
+            if (th.my_row == s.fault[q].row) { a.fault_log[slot].r_row = rres; a.fault_log[slot].tau_row = taur; }
+            if (th.my_col == s.fault[q].col) { a.fault_log[slot].r_col = cres; a.fault_log[slot].tau_col = tauc; }
+            if (th.tid == 0) a.fault_log[slot].check_step = t;
+        }
+        flogged = fnext;
+    }
+    __syncthreads();
+
+    int nr = 0, ncl = 0, fr = -1, fc = -1;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        nr += s.census[w][0];
+        ncl += s.census[w][2];
+        if (fr < 0) fr = s.census[w][1];
+        if (fc < 0) fc = s.census[w][3];
+    }
+    if (nr + ncl == 0) return;
+
+    // rare path: something was flagged (uniform branch)
+    const bool correct = (FT == 2) && nr == 1 && ncl == 1;
+    if (th.my_row >= 0 && th.my_row == fr) { s.bc[0] = Rr; s.bc[1] = rres; s.bc[2] = taur; }
+    if (th.my_col >= 0 && th.my_col == fc) { s.bc[3] = cres; s.bc[4] = tauc; }
+    // Coordinates of (fr, fc) in the accumulator layout; all but the lane
+    // tests are uniform, so the block is picked by scalar branches and the
+    // element by per-lane selects.
+    const int fbi = correct ? (fr % TM) / 32 : -1;
+    const int fjr = correct ? fc % TN : 0;
+    const int fbj = fjr / 32, fjj = fjr % 32;
+    const int freg = ((fjj >> 3) << 2) | (fjj & 3);
+    const bool row_lane = correct && wm == fr / TM && l32 == (fr & 31);
+    const bool own = row_lane && wn == fc / TN && hh == ((fjj >> 2) & 1);
+    float oldv = 0.f;
+    if (correct && wm == fr / TM) {
+        // sum of row fr over this wave's columns, without element (fr, fc)
+        float part = 0.f;
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi) {
+            if (bi == fbi) {
+#pragma unroll
+                for (int bj = 0; bj < NI; ++bj)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float x = acc[bi][bj][r];
+                        const bool hit = own && bj == fbj && r == freg;
+                        part += hit ? 0.f : x;
+                        oldv = hit ? x : oldv;
+                    }
+            }
+        }
+        part = row_lane ? part : 0.f;
+        part += __shfl_xor(part, 32);
+        float* dst = (lane == (fr & 31)) ? &s.excl[wn] : &s.dummy[lane];
+        *dst = part;
+    }
+    __syncthreads();
+    if (correct) {
+        // P_ij = R_i - sum_{j' != j} P_ij'
+        float excl = 0.f;
+#pragma unroll
+        for (int w = 0; w < WN; ++w) excl += s.excl[w];
+        const float newv = s.bc[0] - excl;
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NI; ++bj) {
+                if (bi == fbi && bj == fbj) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[bi][bj][r] = (own && r == freg) ? newv : acc[bi][bj][r];
+                }
+            }
+        if (own) {
+            const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+            atomicAdd(&a.counters[CNT_DETECTED], 1u);
+            atomicAdd(&a.counters[CNT_CORRECTED], 1u);
+            if ((int)e < a.event_cap) {
+                ftgemm_event_t E;
+                E.problem = a.problem; E.tile_m = th.tm; E.tile_n = th.tn; E.kstep = t;
+                E.row = fr; E.col = fc; E.kind = FTGEMM_EV_CORRECTED; E.n_rows = 1; E.n_cols = 1;
+                E.pad_ = 0; E.value_before = oldv; E.value_after = newv;
+                E.r_row = s.bc[1]; E.r_col = s.bc[3]; E.tau_row = s.bc[2]; E.tau_col = s.bc[4];
+                a.events[e] = E;
+            }
+        }
+    } else {
+        int kind;
+        if constexpr (FT == 1) kind = FTGEMM_EV_DETECTED;
+        else kind = (nr == 1 && ncl == 0) ? FTGEMM_EV_CHECKSUM_ROW
+                  : (nr == 0 && ncl == 1) ? FTGEMM_EV_CHECKSUM_COL
+                  : FTGEMM_EV_UNCORRECTABLE;
+        if constexpr (FT == 2) {   // re-base the flagged checksums on the accumulator
+            if (rf) Rr += rres;
+            if (cf) Sc += cres;
+        }
+        if (th.tid == 0) {
+            const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+            atomicAdd(&a.counters[CNT_DETECTED], 1u);
+            if (kind == FTGEMM_EV_UNCORRECTABLE) atomicAdd(&a.counters[CNT_UNCORRECTABLE], 1u);
+            if (kind == FTGEMM_EV_CHECKSUM_ROW || kind == FTGEMM_EV_CHECKSUM_COL)
+                atomicAdd(&a.counters[CNT_CHECKSUM_ONLY], 1u);
+            if ((int)e < a.event_cap) {
+                ftgemm_event_t E;
+                E.problem = a.problem; E.tile_m = th.tm; E.tile_n = th.tn; E.kstep = t;
+                E.row = fr; E.col = fc; E.kind = kind; E.n_rows = nr; E.n_cols = ncl; E.pad_ = 0;
+                E.value_before = E.value_after = 0.f;
+                E.r_row = fr >= 0 ? s.bc[1] : 0.f; E.tau_row = fr >= 0 ? s.bc[2] : 0.f;
+                E.r_col = fc >= 0 ? s.bc[3] : 0.f; E.tau_col = fc >= 0 ? s.bc[4] : 0.f;
+                a.events[e] = E;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// epilogue: C = alpha * scale * P + beta * C (beta == 0: C is not read)
+// ---------------------------------------------------------------------------
+template <class G>
+__device__ __forceinline__ void epilogue(const Acc<G>& acc, const LaunchArgs& a, const Thread& th, float scale) {
+    const float alpha = a.alpha * scale;
+#pragma unroll
+    for (int bi = 0; bi < G::MI; ++bi) {
+        const int i = th.wm * G::TM + 32 * bi + th.l32;
+#pragma unroll
+        for (int bj = 0; bj < G::NI; ++bj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = th.wn * G::TN + 32 * bj + 8 * (r >> 2) + 4 * th.hh + (r & 3);
+                if (i < th.mI && j < th.nJ) {
+                    float* pc = a.C + (size_t)(th.j0 + j) * a.ldc + (th.i0 + i);
+                    float v = alpha * acc[bi][bj][r];
+                    if (a.beta != 0.0f) v = fmaf(a.beta, *pc, v);
+                    *pc = v;
+                }
+            }
+    }
+}
+
+}  // namespace abft
+}  // namespace ftgemm_impl

@@ -51,15 +51,25 @@ struct DeviceGuard {
 
 int default_interval(int k_step) { return std::max(1, 256 / std::max(1, k_step)); }
 
-int select_fp32(int64_t m, int64_t n, ftgemm_config_t* out) {
-    const int nv = fp32_variant_count();
+int variant_count(int dtype) { return dtype == FTGEMM_BF16 ? bf16_variant_count() : fp32_variant_count(); }
+Variant variant_at(int dtype, int v) { return dtype == FTGEMM_BF16 ? bf16_variant(v) : fp32_variant(v); }
+int find_variant(int dtype, const ftgemm_config_t& c) {
+    return dtype == FTGEMM_BF16 ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step)
+                                : fp32_find_variant(c.m_tile, c.n_tile, c.k_step);
+}
+bool dtype_supported(int dtype) { return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16; }
+
+// Largest compiled tile that still gives every compute unit a workgroup,
+// else the smallest tile; a check every 256 k.
+int select_variant(int dtype, int64_t m, int64_t n, ftgemm_config_t* out) {
+    const int nv = variant_count(dtype);
     int pick = nv - 1;
     for (int v = 0; v < nv; ++v) {
-        const Variant x = fp32_variant(v);
+        const Variant x = variant_at(dtype, v);
         const int64_t tiles = ((m + x.m_tile - 1) / x.m_tile) * ((n + x.n_tile - 1) / x.n_tile);
         if (tiles >= kNumCUs) { pick = v; break; }
     }
-    const Variant x = fp32_variant(pick);
+    const Variant x = variant_at(dtype, pick);
     out->m_tile = x.m_tile;
     out->n_tile = x.n_tile;
     out->k_step = x.k_step;
@@ -103,14 +113,14 @@ int ftgemm_select_config(int dtype, int64_t m, int64_t n, int64_t k, int ft_leve
     (void)k;
     (void)ft_level;
     if (!config) return FTGEMM_INVALID;
-    if (dtype != FTGEMM_F32) return FTGEMM_UNSUPPORTED;
-    return select_fp32(m, n, config);
+    if (!dtype_supported(dtype)) return FTGEMM_UNSUPPORTED;
+    return select_variant(dtype, m, n, config);
 }
 
 int ftgemm_create(ftgemm_t* handle, int dtype, int device) {
     if (!handle) return FTGEMM_INVALID;
     *handle = nullptr;
-    if (dtype != FTGEMM_F32) return FTGEMM_UNSUPPORTED;
+    if (!dtype_supported(dtype)) return FTGEMM_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FTGEMM_UNSUPPORTED;
     hipDeviceProp_t prop;
@@ -164,7 +174,7 @@ int ftgemm_set_config(ftgemm_t h, const ftgemm_config_t* c) {
         return FTGEMM_OK;
     }
     if (c->check_interval < 1) return FTGEMM_INVALID;
-    if (fp32_find_variant(c->m_tile, c->n_tile, c->k_step) < 0) return FTGEMM_UNSUPPORTED;
+    if (find_variant(h->dtype, *c) < 0) return FTGEMM_UNSUPPORTED;
     h->cfg = *c;
     h->forced = true;
     return FTGEMM_OK;
@@ -227,7 +237,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
         if (report) report->bad_arg = bad;
         return FTGEMM_INVALID;
     }
-    if (h->dtype != FTGEMM_F32) return FTGEMM_UNSUPPORTED;
+    if (!dtype_supported(h->dtype)) return FTGEMM_UNSUPPORTED;
     const float c = tol > 0.f ? tol : 2.0f;
     if (report) report->tol_used = c;
     if (m == 0 || n == 0) return FTGEMM_OK;
@@ -248,8 +258,8 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
 
     ftgemm_config_t cfg;
     if (h->forced) cfg = h->cfg;
-    else select_fp32(m, n, &cfg);
-    const int variant = fp32_find_variant(cfg.m_tile, cfg.n_tile, cfg.k_step);
+    else select_variant(h->dtype, m, n, &cfg);
+    const int variant = find_variant(h->dtype, cfg);
     if (variant < 0) return FTGEMM_UNSUPPORTED;
 
     const bool inject = h->n_faults > 0;
@@ -267,6 +277,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     a.K = (int32_t)k;
     a.alpha = alpha;
     a.beta = beta;
+    a.scale = h->dtype == FTGEMM_F32 ? 1.0f : h->scale_a * h->scale_b;
     a.tol_c = c;
     a.check_interval = cfg.check_interval;
     a.ft_level = ft_level;
@@ -278,7 +289,8 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     a.n_faults = inject ? h->n_faults : 0;
     a.fault_log = h->d_flog;
     a.fault_log_cap = h->flog_cap;
-    FT_HIP(launch_fp32(variant, inject, a, stream));
+    if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16(variant, inject, a, stream));
+    else FT_HIP(launch_fp32(variant, inject, a, stream));
 
     if (!report) return FTGEMM_OK;
 

@@ -29,6 +29,7 @@ struct LaunchArgs {
     int64_t lda, ldb, ldc;
     int32_t M, N, K;
     float alpha, beta;
+    float scale;                 // per-tensor dequantisation scale_a * scale_b (1 for FP32)
     float tol_c;                 // threshold factor c
     int32_t check_interval;      // g, in k-steps
     int32_t ft_level;            // 0, 1, 2
@@ -51,9 +52,15 @@ int fp32_variant_count();
 Variant fp32_variant(int idx);
 int fp32_find_variant(int m_tile, int n_tile, int k_step);
 
-// Launch the FP32 kernel variant `idx`.  `inject` selects the instantiation
+// Launch the FP32 kernel variant `idx` (A, B as float).  `inject` selects the instantiation
 // carrying the fault-injection hook.  Returns a hipError_t.
 hipError_t launch_fp32(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+
+// Kernel variants for BF16 operands (A, B as bfloat16 codes).
+int bf16_variant_count();
+Variant bf16_variant(int idx);
+int bf16_find_variant(int m_tile, int n_tile, int k_step);
+hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 
 // C = beta * C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t stream);

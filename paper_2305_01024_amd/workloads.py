@@ -153,3 +153,22 @@ def rate_schedule(g: np.random.Generator, rate_per_s: float, t_launch_s: float, 
         return np.zeros(launches, dtype=np.int64), 0
     counts = np.bincount(g.integers(0, launches, size=total), minlength=launches)
     return counts, total
+
+
+# ---------------------------------------------------------------------------
+# low-precision operands (input preparation: rounding to the storage format)
+# ---------------------------------------------------------------------------
+def to_bf16_codes(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to bfloat16 (round to nearest, ties to even) and
+    return the 16-bit codes (finite inputs)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16).reshape(np.shape(x))
+
+
+def quantize_bf16(x: np.ndarray):
+    """bfloat16 codes of x (column-major kept) and the per-tensor scale.
+    bfloat16 shares FP32's exponent range, so no rescaling is needed and the
+    scale is 1."""
+    codes = np.asfortranarray(to_bf16_codes(np.asarray(x, dtype=np.float32)))
+    return codes, 1.0
