@@ -31,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2516.6
 METRIC = "FT-GEMM TFLOP/s & %MFMA peak vs plain GEMM (same GPU), overhead %, detect/correct rate"
 
 
@@ -44,6 +45,9 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--size", type=int, default=8192)
+    p.add_argument("--dtype", choices=("f32", "bf16"), default="f32",
+                   help="f32: the FP32 square workload (beta = 1); bf16: A, B heavy-tailed N(0,1) "
+                        "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel)")
     p.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     p.add_argument("--skip-injection", action="store_true", help="do not run the injection-rate sweep")
     p.add_argument("--plain-only", action="store_true", help="time only the FT-off kernel (profiling)")
@@ -117,22 +121,36 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     N = args.size
     m = n = k = N
-    log(f"generating inputs {m}x{n}x{k}")
-    A = W.normal((m, k), 2, W.STREAM_A)
-    B = W.normal((k, n), 2, W.STREAM_B)
-    C0 = W.normal((m, n), 2, W.STREAM_C)
-    dA = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
-    dB = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
+    bf16 = args.dtype == "bf16"
+    log(f"generating {args.dtype} inputs {m}x{n}x{k}")
+    if bf16:
+        A = W.heavy_tailed((m, k), 4, W.STREAM_A)
+        B = W.heavy_tailed((k, n), 4, W.STREAM_B)
+        Ac, _ = W.quantize_bf16(A)
+        Bc, _ = W.quantize_bf16(B)
+        dA = torch.from_numpy(np.ascontiguousarray(Ac.T).view(np.int16)).cuda()
+        dB = torch.from_numpy(np.ascontiguousarray(Bc.T).view(np.int16)).cuda()
+        C0 = np.zeros((m, n), np.float32, order="F")
+        beta = 0.0
+    else:
+        A = W.normal((m, k), 2, W.STREAM_A)
+        B = W.normal((k, n), 2, W.STREAM_B)
+        C0 = W.normal((m, n), 2, W.STREAM_C)
+        dA = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+        dB = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
+        beta = 1.0
     dC0 = torch.from_numpy(np.ascontiguousarray(C0.T)).cuda()
     dC = dC0.clone()
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
-    h = F.ftgemm_create(F.F32, 0)
-    cfg = F.ftgemm_select_config(F.F32, m, n, k)
+    dtype = F.BF16 if bf16 else F.F32
+    peak = PEAK_BF16_MFMA_TFLOPS if bf16 else PEAK_FP32_MFMA_TFLOPS
+    h = F.ftgemm_create(dtype, 0)
+    cfg = F.ftgemm_select_config(dtype, m, n, k)
     flop = 2.0 * m * n * k
 
     def call(level, report=None):
-        return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, 1.0, dC.data_ptr(), m,
+        return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, beta, dC.data_ptr(), m,
                             level, 0.0, sh, report)
 
     if args.probe:
@@ -146,7 +164,8 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         F.ftgemm_destroy(h)
-        print(json.dumps({"probe": True, "copy_bytes": src.numel() * 4, "m": m, "n": n, "k": k}), flush=True)
+        print(json.dumps({"probe": True, "dtype": args.dtype, "copy_bytes": src.numel() * 4, "m": m, "n": n,
+                          "k": k, "source_sha256": kernel_source_hash(args.dtype)}), flush=True)
         return
 
     # a checked run first: the clean production path must raise no event
@@ -166,7 +185,7 @@ def main():
 
     # fault injection at a rate per second of GEMM time, bit flips in bits 0..30
     injection = None
-    if not args.skip_injection and ms_ft:
+    if not args.skip_injection and ms_ft and not bf16:
         injection = {}
         g = W.rng(2, W.STREAM_SITES)
         launches = 8
@@ -191,12 +210,19 @@ def main():
             log(f"injection {rate}/s: {agg}")
 
     cpu = None
-    if not args.skip_cpu:
+    if not args.skip_cpu and not bf16:
         cpu = cpu_baseline(A, B, C0, cfg)
 
     F.ftgemm_destroy(h)
     ms = ms_ft if ms_ft else ms_plain
     tf = tf_ft if tf_ft else tf_plain
+    kname = f"ftgemm_{args.dtype}_kernel<{cfg.m_tile},{cfg.n_tile},{cfg.k_step}>"
+    traffic, traffic_src = measured_traffic(args.dtype, N) if ms_ft else (None, None)
+    if bf16:
+        workload = f"bf16 square FT-GEMM M=N=K={N}, A,B~N(0,1) with 1% x100, bf16 RNE, alpha=1, beta=0, " \
+                   f"online detect+correct"
+    else:
+        workload = f"fp32 square FT-GEMM M=N=K={N}, A,B,C~N(0,1), alpha=1, beta=1, online detect+correct"
     out = {
         "metric": METRIC,
         "value": round(tf, 3),
@@ -208,24 +234,62 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"fp32 square FT-GEMM M=N=K={N}, A,B,C~N(0,1), alpha=1, beta=1, "
-                               f"online detect+correct", "m": m, "n": n, "k": k,
+        "config": {"workload": workload, "m": m, "n": n, "k": k,
                    "tile": [cfg.m_tile, cfg.n_tile], "k_step": cfg.k_step,
                    "check_interval": cfg.check_interval},
         "ft_tflops": round(tf_ft, 3) if tf_ft else None,
         "plain_tflops": round(tf_plain, 3) if tf_plain else None,
         "ft_overhead_pct": round(100.0 * (ms_ft / ms_plain - 1.0), 3) if (ms_ft and ms_plain) else None,
-        "mfma_frac_ft": round(tf_ft / PEAK_FP32_MFMA_TFLOPS, 4) if tf_ft else None,
-        "mfma_frac_plain": round(tf_plain / PEAK_FP32_MFMA_TFLOPS, 4) if tf_plain else None,
-        "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-                     "kernel": "ftgemm_f32_kernel<256,256,32,2,4,FT=2>" if ms_ft else "ftgemm_f32_kernel FT=0"},
+        "mfma_frac_ft": round(tf_ft / peak, 4) if tf_ft else None,
+        "mfma_frac_plain": round(tf_plain / peak, 4) if tf_plain else None,
+        "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM fetch + write, calibrated)",
+                     "traffic_source": traffic_src,
+                     "kernel": kname + (" FT=2" if ms_ft else " FT=0")},
         "injection": injection,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+KERNEL_SOURCES = {
+    "f32": ("ftgemm_fp32.hip", "ftgemm_abft.hpp", "ftgemm_internal.h"),
+    "bf16": ("ftgemm_bf16.hip", "ftgemm_abft.hpp", "ftgemm_internal.h"),
+}
+
+
+def kernel_source_hash(dtype: str) -> str:
+    """sha256 over the device sources of the kernel the bench times."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for name in KERNEL_SOURCES[dtype]:
+        with open(os.path.join(ROOT, "paper_2305_01024_amd", "csrc", name), "rb") as f:
+            hsh.update(f.read())
+    return hsh.hexdigest()
+
+
+def measured_traffic(dtype: str, size: int):
+    """HBM bytes per launch of the FT kernel from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter
+    reads for an elementwise copy of known size), or None when there is none
+    for this workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"ftgemm_{dtype}_{size}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    blk = text.split("```json", 1)[1].split("```", 1)[0] if "```json" in text else None
+    if blk is None:
+        return None, None
+    rec = json.loads(blk)
+    if rec.get("source_sha256") != kernel_source_hash(dtype):
+        return None, os.path.relpath(path, ROOT) + " (stale: kernel sources changed)"
+    kib = 1024.0
+    fetch = rec["ft_fetch_kib"] * kib * rec["copy_bytes_read"] / (rec["copy_fetch_kib"] * kib)
+    write = rec["ft_write_kib"] * kib * rec["copy_bytes_written"] / (rec["copy_write_kib"] * kib)
+    return int(round(fetch + write)), os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(A, B, C0, cfg, target_s: float = 12.0):
