@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--size", type=int, default=8192)
+    p.add_argument("--workload", choices=("square", "batched", "irregular"), default="square",
+                   help="square: the headline FP32 8192^3 (default); batched: 1024 uneven FP32/BF16 "
+                        "problems in one persistent launch vs a loop of launches; irregular: tall-skinny, "
+                        "small-K and odd shapes, autotuned vs fixed configuration")
     p.add_argument("--dtype", choices=("f32", "bf16"), default="f32",
                    help="f32: the FP32 square workload (beta = 1); bf16: A, B heavy-tailed N(0,1) "
                         "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel)")
@@ -119,6 +123,10 @@ def main():
     from paper_2305_01024_amd import workloads as W
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "irregular":
+        return bench_irregular(args)
     N = args.size
     m = n = k = N
     bf16 = args.dtype == "bf16"
@@ -253,6 +261,169 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _line(metric_value, ms, unit, dtype, config, extra, args, higher=True):
+    out = {"metric": METRIC, "value": round(metric_value, 3), "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": higher, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """1024 FT-GEMMs, M, N, K log-uniform in [32, 2048] (seeded), FP32 or BF16
+    by a seeded coin: one persistent launch replayed from a HIP graph, the
+    same launch eagerly, and a loop of one ftgemm_run per problem.  One
+    additive 1e3 fault per 50 problems in a separate injected run."""
+    import torch
+
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    shapes = W.batched_problems(1024, 32, 2048, 5)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2305_01024 + 500)
+    probs = F.make_problems(len(shapes))
+    keep = []
+    flop = 0.0
+    for p, b in enumerate(shapes):
+        A = torch.randn(b.k, b.m, device="cuda", generator=gen)        # column-major m x k
+        B = torch.randn(b.n, b.k, device="cuda", generator=gen)        # column-major k x n
+        C = torch.zeros(b.n, b.m, device="cuda")
+        if b.dtype == "bf16":
+            A = A.to(torch.bfloat16).view(torch.int16)
+            B = B.to(torch.bfloat16).view(torch.int16)
+        keep.append((A, B, C))
+        q = probs[p]
+        q["dtype"] = F.BF16 if b.dtype == "bf16" else F.F32
+        q["m"], q["n"], q["k"] = b.m, b.n, b.k
+        q["lda"], q["ldb"], q["ldc"] = b.m, b.k, b.m
+        q["alpha"], q["beta"], q["scale_a"], q["scale_b"] = 1.0, 0.0, 1.0, 1.0
+        q["A"], q["B"], q["C"] = A.data_ptr(), B.data_ptr(), C.data_ptr()
+        flop += 2.0 * b.m * b.n * b.k
+    stream = torch.cuda.current_stream()
+    h = F.ftgemm_create(F.F32, 0)
+    hb = F.ftgemm_create(F.BF16, 0)
+    rates = F.ftgemm_tune_batched(h, stream.cuda_stream)
+    log(f"batched: {len(shapes)} problems, {flop / 1e12:.3f} TFLOP; variant rates {rates}")
+    rep = F.ReportBuffer(64)
+    st = F.ftgemm_batched(h, probs, F.FT_CORRECT, 0.0, stream.cuda_stream, rep)
+    assert st == F.OK and rep.report.n_events == 0
+
+    def batched():
+        F.ftgemm_batched(h, probs, F.FT_CORRECT, 0.0, stream.cuda_stream)
+
+    def loop():
+        for p, b in enumerate(shapes):
+            hh = hb if b.dtype == "bf16" else h
+            A, B, C = keep[p]
+            F.ftgemm_run(hh, b.m, b.n, b.k, 1.0, A.data_ptr(), b.m, B.data_ptr(), b.k, 0.0, C.data_ptr(), b.m,
+                         F.FT_CORRECT, 0.0, stream.cuda_stream, None)
+
+    ms_eager = timed(batched, args.steps, args.warmup, stream)
+    ms_loop = timed(loop, max(1, args.steps // 4), 1, stream)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        batched()                      # same problem list: the cached plan
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        F.ftgemm_batched(h, probs, F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream)
+    ms_graph = timed(graph.replay, args.steps, args.warmup, stream)
+    # injection: one additive fault per 50 problems
+    g = W.rng(5, W.STREAM_SITES)
+    chosen = sorted(g.choice(len(shapes), size=len(shapes) // 50, replace=False).tolist())
+    sites = []
+    for p in chosen:
+        b = shapes[p]
+        c = F.ftgemm_batched_config(h, p).as_tuple()
+        s_ = W.fault_sites(g, b.m, b.n, b.k, c[0], c[1], c[2], c[3], 1, payload=1e3)
+        s_["problem"] = p
+        sites.append(s_)
+    sites = np.concatenate(sites)
+    sites = sites[np.lexsort((sites["kstep"], sites["tile_n"], sites["tile_m"], sites["problem"]))]
+    F.ftgemm_set_injection(h, sites)
+    rep = F.ReportBuffer(4096)
+    F.ftgemm_batched(h, probs, F.FT_CORRECT, 0.0, stream.cuda_stream, rep)
+    flog = F.ftgemm_get_injection_log(h)
+    F.ftgemm_set_injection(h, None)
+    corrected = {(int(e["problem"]), int(e["tile_m"]), int(e["tile_n"]), int(e["row"]), int(e["col"]))
+                 for e in rep.events if int(e["kind"]) == F.EV_CORRECTED}
+    hit = sum((int(x["problem"]), int(x["tile_m"]), int(x["tile_n"]), int(x["row"]), int(x["col"])) in corrected
+              for x in flog)
+    F.ftgemm_destroy(h)
+    F.ftgemm_destroy(hb)
+    tf = flop / (ms_graph * 1e-3) / 1e12
+    _line(tf, ms_graph, "TFLOP/s", "f32+bf16",
+          {"workload": "batched FT-GEMM: 1024 problems, M,N,K log-uniform [32,2048], FP32/BF16 by a fair coin, "
+                       "alpha=1, beta=0, online detect+correct, one persistent launch replayed from a HIP graph",
+           "problems": len(shapes), "tflop": round(flop / 1e12, 4)},
+          {"eager_batched_ms": round(ms_eager, 4), "loop_of_launches_ms": round(ms_loop, 4),
+           "graph_vs_loop_speedup": round(ms_loop / ms_graph, 3),
+           "variant_rates_mac_per_s": [float(r) for r in rates],
+           "injection": {"injected": int(len(flog)), "corrected_at_site": int(hit),
+                         "events": int(rep.report.n_events), "uncorrectable": int(rep.report.uncorrectable)},
+           "roofline": None, "cpu_baseline": None}, args)
+
+
+def bench_irregular(args):
+    """The irregular FP32 shapes, U[-1,1], beta = 0: the configuration the
+    autotuner picks (check at most every 256 k) against the fixed 256 x 256 x
+    32, g = 8 one; then 100 exponent-bit flips per second of GEMM time."""
+    import torch
+
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    stream = torch.cuda.current_stream()
+    h = F.ftgemm_create(F.F32, 0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2305_01024 + 300)
+    rows = []
+    total_flop = total_ms = 0.0
+    for (m, n, k) in W.irregular_shapes(3):
+        A = torch.rand(k, m, device="cuda", generator=gen) * 2 - 1
+        B = torch.rand(n, k, device="cuda", generator=gen) * 2 - 1
+        C = torch.zeros(n, m, device="cuda")
+
+        def call(level=F.FT_CORRECT):
+            F.ftgemm_run(h, m, n, k, 1.0, A.data_ptr(), m, B.data_ptr(), k, 0.0, C.data_ptr(), m, level, 0.0,
+                         stream.cuda_stream, None)
+        F.ftgemm_set_config(h, (256, 256, 32, 8))
+        ms_fixed = timed(call, args.steps, args.warmup, stream)
+        F.ftgemm_set_config(h, None)
+        cfg = F.ftgemm_tune(h, m, n, k, F.FT_CORRECT, 256, stream.cuda_stream).as_tuple()
+        ms_tuned = timed(call, args.steps, args.warmup, stream)
+        ms_plain = timed(lambda: call(F.FT_OFF), args.steps, args.warmup, stream)
+        flop = 2.0 * m * n * k
+        g = W.rng(3, W.STREAM_SITES)
+        counts, _ = W.rate_schedule(g, 100, ms_tuned * 1e-3, 4)
+        inj = dict(injected=0, corrected=0, events=0)
+        for c_l in counts:
+            sites = W.fault_sites(g, m, n, k, cfg[0], cfg[1], cfg[2], cfg[3], int(c_l), kind=W.KIND_XOR,
+                                  bits=range(23, 31))
+            F.ftgemm_set_injection(h, sites if len(sites) else None)
+            rep = F.ReportBuffer(1024)
+            F.ftgemm_run(h, m, n, k, 1.0, A.data_ptr(), m, B.data_ptr(), k, 0.0, C.data_ptr(), m, F.FT_CORRECT,
+                         0.0, stream.cuda_stream, rep)
+            inj["injected"] += len(sites)
+            inj["corrected"] += int(rep.report.corrected)
+            inj["events"] += int(rep.report.n_events)
+        F.ftgemm_set_injection(h, None)
+        rows.append({"shape": [m, n, k], "tuned_config": list(cfg), "tuned_tflops": round(flop / ms_tuned / 1e9, 2),
+                     "fixed_tflops": round(flop / ms_fixed / 1e9, 2), "plain_tflops": round(flop / ms_plain / 1e9, 2),
+                     "injection_100_per_s": inj})
+        log(f"irregular {m}x{n}x{k}: {rows[-1]}")
+        total_flop += flop
+        total_ms += ms_tuned
+    F.ftgemm_destroy(h)
+    _line(total_flop / (total_ms * 1e-3) / 1e12, total_ms, "TFLOP/s", "f32",
+          {"workload": "FP32 irregular FT-GEMM shapes (65536,256,4096), (256,65536,4096), (16384,16384,64), "
+                       "(3001,1999,4097), U[-1,1], beta=0, autotuned configuration, one call per shape per step"},
+          {"shapes": rows, "roofline": None, "cpu_baseline": None}, args)
 
 
 KERNEL_SOURCES = {

@@ -121,6 +121,8 @@ typedef struct {
     ftgemm_config_t config;   /* configuration the call used */
     int32_t bad_arg;          /* 1-based position of an invalid argument, else 0 */
     float tol_used;           /* threshold factor c the call used */
+    int32_t bad_problem;      /* ftgemm_batched: index of the invalid problem, else -1 */
+    int32_t pad_;
 } ftgemm_report_t;
 
 /* Create a handle on `device` for operands of type `dtype`.  Allocates the
@@ -163,6 +165,68 @@ int ftgemm_run(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
                const void* A, int64_t lda, const void* B, int64_t ldb, float beta,
                float* C, int64_t ldc, int ft_level, float tol, hipStream_t stream,
                ftgemm_report_t* report);
+
+/* One problem of a batched call: C = alpha * (scale_a A) (scale_b B) +
+ * beta * C, column-major as in ftgemm_run, with its own dtype (FTGEMM_F32 or
+ * FTGEMM_BF16), sizes, scales and device pointers (96 bytes). */
+typedef struct {
+    int32_t dtype;
+    int32_t reserved_;        /* must be 0 */
+    int64_t m, n, k, lda, ldb, ldc;
+    float alpha, beta, scale_a, scale_b;
+    const void* A;
+    const void* B;
+    float* C;
+} ftgemm_problem_t;
+
+/* Many independent FT-GEMMs in one persistent launch (section 4.2.3 ABFT per
+ * output tile, applied to every tile of every problem).  Each problem gets
+ * its tile shape from the batched tile variants (FP32 128x128 or 64x64, BF16
+ * 128x128) by the cost model of ftgemm_tune_batched, and a check every 256 k.
+ * The workgroups of a persistent grid walk a cost-ordered list of (problem,
+ * tile) items.  Events carry the problem index.  The per-problem plan is
+ * built on the host and kept in the handle: a call with the same problem
+ * list as the previous batched call on this handle copies nothing and
+ * allocates nothing, so with report == NULL it can be captured into a HIP
+ * graph (a different list under stream capture returns FTGEMM_INVALID with
+ * bad_arg 3).  An invalid problem returns FTGEMM_INVALID with bad_arg 3 and
+ * its index in report->bad_problem.  FP8 problems are not supported here. */
+int ftgemm_batched(ftgemm_t handle, int count, const ftgemm_problem_t* probs, int ft_level, float tol,
+                   hipStream_t stream, ftgemm_report_t* report);
+
+/* The configuration the handle's current batched plan uses for problem p
+ * (zeros for a problem with no tiles or only the C = beta C update). */
+int ftgemm_batched_config(ftgemm_t handle, int p, ftgemm_config_t* config);
+
+/* Autotuner, in place of the paper's kernel-template generator: times every
+ * compiled tile variant of the handle's dtype, each with the check intervals
+ * of 1, 2, 4, ... k-steps up to max_k_between_checks (0 = 256) columns of k,
+ * on operands of shape (m, n, k) allocated for the purpose (filled with
+ * zeros, freed before return), and keeps the fastest configuration for this
+ * shape and ft_level in the handle; later ftgemm_run calls with the same
+ * shape and level use it unless a configuration is forced.  *best receives
+ * it.  Synchronises `stream`. */
+int ftgemm_tune(ftgemm_t handle, int64_t m, int64_t n, int64_t k, int ft_level, int max_k_between_checks,
+                hipStream_t stream, ftgemm_config_t* best);
+
+/* Tuned configurations held by the handle, for persisting them: copy up to
+ * cap entries into out (shape and level in the first four int64 of each
+ * entry: m, n, k, ft_level; then the configuration); *n receives the count.
+ * ftgemm_add_tuned inserts one entry (replacing one for the same key). */
+typedef struct {
+    int64_t m, n, k, ft_level;
+    ftgemm_config_t config;
+} ftgemm_tuned_t;
+int ftgemm_get_tuned(ftgemm_t handle, ftgemm_tuned_t* out, int cap, int* n);
+int ftgemm_add_tuned(ftgemm_t handle, const ftgemm_tuned_t* entry);
+
+/* Cost model of ftgemm_batched: the batched tile variants' throughput, in
+ * multiply-adds per second, measured by one timed batched launch per variant
+ * on 64 problems of 512 x 512 x 512 with operands allocated for the purpose.
+ * Without it the model uses built-in relative rates.  rates (may be NULL)
+ * receives the measured value per variant (3 entries: FP32 128x128,
+ * FP32 64x64, BF16 128x128).  Synchronises `stream`. */
+int ftgemm_tune_batched(ftgemm_t handle, hipStream_t stream, double* rates);
 
 /* Fault injection hook (compiled into dedicated kernel instantiations; the
  * production kernels contain no injection code).  `faults` is a host array

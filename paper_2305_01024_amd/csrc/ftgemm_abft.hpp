@@ -27,27 +27,51 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 // ---------------------------------------------------------------------------
 // lane exchanges (wave64)
 // ---------------------------------------------------------------------------
-// Partner value for the exchange level on lane bit BIT.  Levels 0-3 stay
-// inside a 16-lane row and use DPP (no LDS round trip): quad_perm [1,0,3,2]
-// (partner l^1), quad_perm [3,2,1,0] (l^3), row_half_mirror (l^7 within 8)
-// and row_ror:8 (l^8); level 4 is an LDS swizzle (l^16), level 5 a permute
-// (l^32).  Each pairs lane l with a lane whose bit BIT differs and whose
-// higher bits agree, which is all a butterfly reduction needs: the sets of
-// lanes summed into each value stay disjoint and end up complete.
+// Partner value for the exchange level on lane bit BIT < 4, with DPP (no LDS
+// round trip).  With EXACT the partner is lane l ^ (1 << BIT): quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], row_shl:4 / row_shr:4 by lane, row_ror:8.
+// Without it, levels 1 and 2 use quad_perm [3,2,1,0] (l ^ 3) and
+// row_half_mirror (l ^ 7 within 8), one instruction each; that is valid only
+// when the reduction continues down to lane bit 0: a butterfly needs the
+// partner's bit BIT to differ and its higher bits to agree, and the lower
+// bits are summed over later.  A reduction that stops above bit 0 keeps the
+// lower bits as separate groups and needs the exact partner.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
 
+template <int BIT, bool EXACT>
+__device__ __forceinline__ float partner(float x, int lane) {
+    static_assert(BIT >= 0 && BIT < 4, "levels 4 and 5 use swap_add");
+    if constexpr (BIT == 0) return dpp_mov<0xB1>(x);                        // quad_perm [1,0,3,2]
+    else if constexpr (BIT == 1) return EXACT ? dpp_mov<0x4E>(x)            // quad_perm [2,3,0,1]
+                                              : dpp_mov<0x1B>(x);           // quad_perm [3,2,1,0]
+    else if constexpr (BIT == 2) {
+        if constexpr (!EXACT) return dpp_mov<0x141>(x);                     // row_half_mirror
+        const float up = dpp_mov<0x104>(x);                                 // row_shl:4: lane i + 4
+        const float dn = dpp_mov<0x114>(x);                                 // row_shr:4: lane i - 4
+        return (lane & 4) ? dn : up;
+    } else return dpp_mov<0x128>(x);                                        // row_ror:8
+}
+
+// Butterfly level on lane bit 4 or 5 without LDS.  v_permlane16_swap_b32
+// exchanges the odd 16-lane rows of its first register with the even rows of
+// its second; v_permlane32_swap_b32 the upper 32 lanes of the first with the
+// lower 32 of the second.  With lo = the value lanes whose bit is clear keep
+// and hi = the value lanes whose bit is set keep, the two results add up, in
+// every lane, to its kept value plus its partner's (lane l ^ 16 or l ^ 32).
 template <int BIT>
-__device__ __forceinline__ float partner(float x) {
-    if constexpr (BIT == 0) return dpp_mov<0xB1>(x);        // quad_perm [1,0,3,2]
-    else if constexpr (BIT == 1) return dpp_mov<0x1B>(x);   // quad_perm [3,2,1,0]
-    else if constexpr (BIT == 2) return dpp_mov<0x141>(x);  // row_half_mirror
-    else if constexpr (BIT == 3) return dpp_mov<0x128>(x);  // row_ror:8
-    else if constexpr (BIT == 4)                            // swizzle: swap 16-lane halves of 32
-        return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
-    else return __shfl_xor(x, 32);
+__device__ __forceinline__ float swap_add(float lo, float hi) {
+    static_assert(BIT == 4 || BIT == 5, "swap levels");
+    const unsigned a = __builtin_bit_cast(unsigned, lo), b = __builtin_bit_cast(unsigned, hi);
+    if constexpr (BIT == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+    }
 }
 
 // Reduce-scatter of N values over the lanes that differ only in lane bits
@@ -60,17 +84,26 @@ template <int N, int BIT, int BLO = 0>
 struct ReduceScatter {
     __device__ __forceinline__ static void run(float* x, int lane) {
         if constexpr (BIT >= BLO && BIT >= 0) {
-            if constexpr (N > 1) {
+            if constexpr (BIT >= 4) {
+                if constexpr (N > 1) {
+#pragma unroll
+                    for (int q = 0; q < N / 2; ++q) x[q] = swap_add<BIT>(x[q], x[q + N / 2]);
+                    ReduceScatter<N / 2, BIT - 1, BLO>::run(x, lane);
+                } else {
+                    x[0] = swap_add<BIT>(x[0], x[0]);
+                    ReduceScatter<1, BIT - 1, BLO>::run(x, lane);
+                }
+            } else if constexpr (N > 1) {
                 const bool up = ((lane >> BIT) & 1) != 0;
 #pragma unroll
                 for (int q = 0; q < N / 2; ++q) {
                     const float send = up ? x[q] : x[q + N / 2];
                     const float keep = up ? x[q + N / 2] : x[q];
-                    x[q] = keep + partner<BIT>(send);
+                    x[q] = keep + partner<BIT, (BLO > 0)>(send, lane);
                 }
                 ReduceScatter<N / 2, BIT - 1, BLO>::run(x, lane);
             } else {
-                x[0] += partner<BIT>(x[0]);
+                x[0] += partner<BIT, (BLO > 0)>(x[0], lane);
                 ReduceScatter<1, BIT - 1, BLO>::run(x, lane);
             }
         }
@@ -80,10 +113,8 @@ struct ReduceScatter {
 // Sum over the 64 lanes of a wave, returned as a wave-uniform value.
 __device__ __forceinline__ float wave_sum(float x) {
     float v[1] = {x};
-    ReduceScatter<1, 4, 0>::run(v, 0);
-    const int lo = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 0);
-    const int hi = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), 32);
-    return __builtin_bit_cast(float, lo) + __builtin_bit_cast(float, hi);
+    ReduceScatter<1, 5, 0>::run(v, 0);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v[0])));
 }
 
 __device__ __forceinline__ float bitflip(float v, int bit) {
@@ -286,7 +317,7 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
     }
 #pragma unroll
     for (int bi = 0; bi < MI; ++bi) {
-        const float rs = rpart[bi] + __shfl_xor(rpart[bi], 32);
+        const float rs = swap_add<5>(rpart[bi], rpart[bi]);
         if (hh == 0) s.rowpart[wn][wm * TM + 32 * bi + l32] = rs;
     }
     // (2) per-wave sums of the row and column norms for the threshold
@@ -380,7 +411,7 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
             }
         }
         part = row_lane ? part : 0.f;
-        part += __shfl_xor(part, 32);
+        part = swap_add<5>(part, part);
         float* dst = (lane == (fr & 31)) ? &s.excl[wn] : &s.dummy[lane];
         *dst = part;
     }

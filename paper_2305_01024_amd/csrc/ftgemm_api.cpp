@@ -2,6 +2,7 @@
 // argument checks, BLAS quick returns, kernel selection and launch, event log
 // and fault-injection plumbing.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -25,6 +26,21 @@ struct ftgemm_ctx {
     int n_faults = 0, fault_cap = 0;
     ftgemm_fault_log_t* d_flog = nullptr;
     int flog_cap = 0;
+    // configurations picked by ftgemm_tune, per (m, n, k, ft_level)
+    std::vector<ftgemm_tuned_t> tuned;
+    // batched plan of the last ftgemm_batched call
+    std::vector<ftgemm_problem_t> plan_probs;
+    std::vector<ftgemm_config_t> plan_cfg;
+    bool plan_valid = false;
+    BatchProblem* d_bprobs = nullptr;
+    int bprobs_cap = 0;
+    BatchItem* d_bitems = nullptr;
+    int bitems_cap = 0;
+    int n_items = 0;
+    int grid = 0;
+    uint64_t plan_checks_per_level[3] = {0, 0, 0};
+    // cost model of the batched tile variants: multiply-adds per second
+    double batch_rate[kBatchVariants] = {4.0e13, 2.0e13, 1.6e14};
 };
 
 namespace {
@@ -51,13 +67,21 @@ struct DeviceGuard {
 
 int default_interval(int k_step) { return std::max(1, 256 / std::max(1, k_step)); }
 
-int variant_count(int dtype) { return dtype == FTGEMM_BF16 ? bf16_variant_count() : fp32_variant_count(); }
-Variant variant_at(int dtype, int v) { return dtype == FTGEMM_BF16 ? bf16_variant(v) : fp32_variant(v); }
-int find_variant(int dtype, const ftgemm_config_t& c) {
-    return dtype == FTGEMM_BF16 ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step)
-                                : fp32_find_variant(c.m_tile, c.n_tile, c.k_step);
+int variant_count(int dtype) {
+    return dtype == FTGEMM_BF16 ? bf16_variant_count() : dtype == FTGEMM_F8E4M3 ? fp8_variant_count()
+                                                                               : fp32_variant_count();
 }
-bool dtype_supported(int dtype) { return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16; }
+Variant variant_at(int dtype, int v) {
+    return dtype == FTGEMM_BF16 ? bf16_variant(v) : dtype == FTGEMM_F8E4M3 ? fp8_variant(v) : fp32_variant(v);
+}
+int find_variant(int dtype, const ftgemm_config_t& c) {
+    return dtype == FTGEMM_BF16     ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step)
+           : dtype == FTGEMM_F8E4M3 ? fp8_find_variant(c.m_tile, c.n_tile, c.k_step)
+                                    : fp32_find_variant(c.m_tile, c.n_tile, c.k_step);
+}
+bool dtype_supported(int dtype) {
+    return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3;
+}
 
 // Largest compiled tile that still gives every compute unit a workgroup,
 // else the smallest tile; a check every 256 k.
@@ -75,6 +99,158 @@ int select_variant(int dtype, int64_t m, int64_t n, ftgemm_config_t* out) {
     out->k_step = x.k_step;
     out->check_interval = default_interval(x.k_step);
     return FTGEMM_OK;
+}
+
+bool find_tuned(const ftgemm_ctx* h, int64_t m, int64_t n, int64_t k, int ft_level, ftgemm_config_t* out) {
+    for (const ftgemm_tuned_t& t : h->tuned)
+        if (t.m == m && t.n == n && t.k == k && t.ft_level == ft_level) {
+            *out = t.config;
+            return true;
+        }
+    return false;
+}
+
+bool dims_ok(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc) {
+    return m >= 0 && m <= INT32_MAX && n >= 0 && n <= INT32_MAX && k >= 0 && k <= INT32_MAX &&
+           lda >= std::max<int64_t>(1, m) && ldb >= std::max<int64_t>(1, k) && ldc >= std::max<int64_t>(1, m);
+}
+
+// Per-problem checks of a batched call; returns the index of the first bad problem or -1.
+int first_bad_problem(int count, const ftgemm_problem_t* probs) {
+    for (int p = 0; p < count; ++p) {
+        const ftgemm_problem_t& q = probs[p];
+        if (q.dtype != FTGEMM_F32 && q.dtype != FTGEMM_BF16) return p;
+        if (q.reserved_ != 0 || !dims_ok(q.m, q.n, q.k, q.lda, q.ldb, q.ldc)) return p;
+        if (q.m > 0 && q.n > 0 && !q.C) return p;
+        if (q.m > 0 && q.n > 0 && q.k > 0 && q.alpha != 0.f && (!q.A || !q.B)) return p;
+        if (q.dtype != FTGEMM_F32 && !(q.scale_a > 0.f && q.scale_b > 0.f)) return p;
+    }
+    return -1;
+}
+
+// Tile variant of the batched kernel for a problem: the one with the least
+// modelled time (padded multiply-adds over the variant's measured rate).
+int pick_batch_variant(const ftgemm_ctx* h, const ftgemm_problem_t& q) {
+    int best = -1;
+    double best_t = 0.0;
+    for (int v = 0; v < kBatchVariants; ++v) {
+        if (batch_variant_dtype(v) != q.dtype) continue;
+        const Variant x = batch_variant(v);
+        const double padded = (double)((q.m + x.m_tile - 1) / x.m_tile) * x.m_tile *
+                              (double)((q.n + x.n_tile - 1) / x.n_tile) * x.n_tile *
+                              (double)((q.k + x.k_step - 1) / x.k_step) * x.k_step;
+        const double t = padded / h->batch_rate[v];
+        if (best < 0 || t < best_t) {
+            best = v;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
+template <class T>
+int grow(T** buf, int* cap, int need) {
+    if (need <= *cap) return FTGEMM_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc(buf, sizeof(T) * (size_t)need) != hipSuccess) return FTGEMM_NO_MEMORY;
+    *cap = need;
+    return FTGEMM_OK;
+}
+
+// Build the device plan of a batched call: per-problem descriptors and the
+// cost-ordered (problem, tile) list.
+int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
+    std::vector<BatchProblem> bp((size_t)count);
+    std::vector<ftgemm_config_t> cfgs((size_t)count, ftgemm_config_t{0, 0, 0, 0});
+    struct Work { double cost; BatchItem item; };
+    std::vector<Work> work;
+    uint64_t checks[3] = {0, 0, 0};
+    for (int p = 0; p < count; ++p) {
+        const ftgemm_problem_t& q = probs[p];
+        BatchProblem& d = bp[(size_t)p];
+        std::memset(&d, 0, sizeof(d));
+        d.A = q.A;
+        d.B = q.B;
+        d.C = q.C;
+        d.lda = q.lda;
+        d.ldb = q.ldb;
+        d.ldc = q.ldc;
+        d.M = (int32_t)q.m;
+        d.N = (int32_t)q.n;
+        d.K = (int32_t)q.k;
+        d.alpha = q.alpha;
+        d.beta = q.beta;
+        d.scale = q.dtype == FTGEMM_F32 ? 1.0f : q.scale_a * q.scale_b;
+        if (q.m == 0 || q.n == 0) {
+            d.variant = -1;
+            d.ntm = 1;
+            continue;
+        }
+        int bm = 128, bn = 128;
+        double per_tile = 1.0;
+        if (q.k == 0 || q.alpha == 0.f) {
+            d.variant = -1;
+        } else {
+            d.variant = pick_batch_variant(h, q);
+            const Variant x = batch_variant(d.variant);
+            bm = x.m_tile;
+            bn = x.n_tile;
+            d.check_interval = default_interval(x.k_step);
+            cfgs[(size_t)p] = {x.m_tile, x.n_tile, x.k_step, d.check_interval};
+            const int64_t nk = (q.k + x.k_step - 1) / x.k_step;
+            per_tile = (double)bm * bn * (double)(nk * x.k_step) / h->batch_rate[d.variant];
+            const int64_t tiles = ((q.m + bm - 1) / bm) * ((q.n + bn - 1) / bn);
+            checks[2] += (uint64_t)(tiles * ((nk + d.check_interval - 1) / d.check_interval));
+            checks[1] += (uint64_t)tiles;
+        }
+        d.ntm = (int32_t)((q.m + bm - 1) / bm);
+        const int64_t ntn = (q.n + bn - 1) / bn;
+        for (int64_t t = 0; t < (int64_t)d.ntm * ntn; ++t) work.push_back({per_tile, {p, (int32_t)t}});
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work& x, const Work& y) { return x.cost > y.cost; });
+    std::vector<BatchItem> items(work.size());
+    for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].item;
+    if (grow(&h->d_bprobs, &h->bprobs_cap, std::max(1, count)) != FTGEMM_OK) return FTGEMM_NO_MEMORY;
+    if (grow(&h->d_bitems, &h->bitems_cap, std::max<int>(1, (int)items.size())) != FTGEMM_OK) return FTGEMM_NO_MEMORY;
+    if (count > 0)
+        FT_HIP(hipMemcpy(h->d_bprobs, bp.data(), sizeof(BatchProblem) * (size_t)count, hipMemcpyHostToDevice));
+    if (!items.empty())
+        FT_HIP(hipMemcpy(h->d_bitems, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
+    h->n_items = (int)items.size();
+    h->grid = std::max(1, std::min(h->n_items, batch_resident_blocks(h->device)));
+    h->plan_checks_per_level[0] = 0;
+    h->plan_checks_per_level[1] = checks[1];
+    h->plan_checks_per_level[2] = checks[2];
+    h->plan_probs.assign(probs, probs + count);
+    h->plan_cfg = cfgs;
+    h->plan_valid = true;
+    return FTGEMM_OK;
+}
+
+bool same_plan(const ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
+    return h->plan_valid && (int)h->plan_probs.size() == count &&
+           (count == 0 || std::memcmp(h->plan_probs.data(), probs, sizeof(ftgemm_problem_t) * (size_t)count) == 0);
+}
+
+// Counters and events of the last launch into the report.
+int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, uint64_t checks) {
+    FT_HIP(hipStreamSynchronize(stream));
+    uint32_t cnt[CNT_N];
+    FT_HIP(hipMemcpy(cnt, h->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    report->checks = checks;
+    report->detected = cnt[CNT_DETECTED];
+    report->corrected = cnt[CNT_CORRECTED];
+    report->uncorrectable = cnt[CNT_UNCORRECTABLE];
+    report->checksum_only = cnt[CNT_CHECKSUM_ONLY];
+    const uint32_t logged = std::min<uint32_t>(cnt[CNT_EVENTS], (uint32_t)h->event_cap);
+    const uint32_t copy = report->events ? std::min<uint32_t>(logged, report->cap_events) : 0;
+    if (copy > 0)
+        FT_HIP(hipMemcpy(report->events, h->d_events, sizeof(ftgemm_event_t) * copy, hipMemcpyDeviceToHost));
+    report->n_events = copy;
+    if (cnt[CNT_EVENTS] > copy && report->events) return FTGEMM_LOG_OVERFLOW;
+    return report->uncorrectable > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
 }
 
 }  // namespace
@@ -155,6 +331,8 @@ int ftgemm_destroy(ftgemm_t h) {
         if (h->d_counters) (void)hipFree(h->d_counters);
         if (h->d_faults) (void)hipFree(h->d_faults);
         if (h->d_flog) (void)hipFree(h->d_flog);
+        if (h->d_bprobs) (void)hipFree(h->d_bprobs);
+        if (h->d_bitems) (void)hipFree(h->d_bitems);
     }
     delete h;
     return FTGEMM_OK;
@@ -227,6 +405,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
         report->n_events = 0;
         report->bad_arg = 0;
         report->tol_used = 0.f;
+        report->bad_problem = -1;
         std::memset(&report->config, 0, sizeof(report->config));
     }
     if (!h) {
@@ -258,7 +437,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
 
     ftgemm_config_t cfg;
     if (h->forced) cfg = h->cfg;
-    else select_variant(h->dtype, m, n, &cfg);
+    else if (!find_tuned(h, m, n, k, ft_level, &cfg)) select_variant(h->dtype, m, n, &cfg);
     const int variant = find_variant(h->dtype, cfg);
     if (variant < 0) return FTGEMM_UNSUPPORTED;
 
@@ -290,30 +469,241 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     a.fault_log = h->d_flog;
     a.fault_log_cap = h->flog_cap;
     if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16(variant, inject, a, stream));
+    else if (h->dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8(variant, inject, a, stream));
     else FT_HIP(launch_fp32(variant, inject, a, stream));
 
     if (!report) return FTGEMM_OK;
-
-    FT_HIP(hipStreamSynchronize(stream));
-    uint32_t cnt[CNT_N];
-    FT_HIP(hipMemcpy(cnt, h->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    report->config = cfg;
     const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
     const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
     const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
                            : ft_level == 1 ? 1 : 0;
-    report->checks = (uint64_t)(ntiles * per_tile);
-    report->detected = cnt[CNT_DETECTED];
-    report->corrected = cnt[CNT_CORRECTED];
-    report->uncorrectable = cnt[CNT_UNCORRECTABLE];
-    report->checksum_only = cnt[CNT_CHECKSUM_ONLY];
-    report->config = cfg;
-    const uint32_t logged = std::min<uint32_t>(cnt[CNT_EVENTS], (uint32_t)h->event_cap);
-    const uint32_t copy = report->events ? std::min<uint32_t>(logged, report->cap_events) : 0;
-    if (copy > 0)
-        FT_HIP(hipMemcpy(report->events, h->d_events, sizeof(ftgemm_event_t) * copy, hipMemcpyDeviceToHost));
-    report->n_events = copy;
-    if (cnt[CNT_EVENTS] > copy && report->events) return FTGEMM_LOG_OVERFLOW;
-    return report->uncorrectable > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
+    return fill_report(h, stream, report, (uint64_t)(ntiles * per_tile));
+}
+
+int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_level, float tol,
+                   hipStream_t stream, ftgemm_report_t* report) {
+    if (report) {
+        report->checks = report->detected = report->corrected = 0;
+        report->uncorrectable = report->checksum_only = 0;
+        report->n_events = 0;
+        report->bad_arg = 0;
+        report->tol_used = 0.f;
+        report->bad_problem = -1;
+        std::memset(&report->config, 0, sizeof(report->config));
+    }
+    int bad = 0;
+    if (!h) bad = 1;
+    else if (count < 0 || (count > 0 && !probs)) bad = 2;
+    else if (ft_level < 0 || ft_level > 2) bad = 4;
+    else if (!(tol == tol) || tol > 1e30f) bad = 5;
+    if (bad) {
+        if (report) report->bad_arg = bad;
+        return FTGEMM_INVALID;
+    }
+    const int bp = first_bad_problem(count, probs);
+    if (bp >= 0) {
+        if (report) {
+            report->bad_arg = 3;
+            report->bad_problem = bp;
+        }
+        return FTGEMM_INVALID;
+    }
+    const float c = tol > 0.f ? tol : 2.0f;
+    if (report) report->tol_used = c;
+    DeviceGuard g(h->device);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    FT_HIP(hipStreamIsCapturing(stream, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    const bool inject = h->n_faults > 0;
+    if (capturing && (report || inject)) {
+        if (report) report->bad_arg = 7;
+        return FTGEMM_INVALID;
+    }
+    if (!same_plan(h, count, probs)) {
+        if (capturing) {
+            if (report) report->bad_arg = 3;
+            return FTGEMM_INVALID;
+        }
+        const int st = build_plan(h, count, probs);
+        if (st != FTGEMM_OK) {
+            h->plan_valid = false;
+            return st;
+        }
+    }
+    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
+    BatchArgs b{};
+    b.probs = h->d_bprobs;
+    b.items = h->d_bitems;
+    b.n_items = h->n_items;
+    b.ft_level = ft_level;
+    b.tol_c = c;
+    b.event_cap = h->event_cap;
+    b.events = h->d_events;
+    b.counters = h->d_counters;
+    b.faults = inject ? h->d_faults : nullptr;
+    b.n_faults = inject ? h->n_faults : 0;
+    b.fault_log_cap = h->flog_cap;
+    b.fault_log = h->d_flog;
+    FT_HIP(launch_batched(b, inject, h->grid, stream));
+    if (!report) return FTGEMM_OK;
+    return fill_report(h, stream, report, h->plan_checks_per_level[ft_level]);
+}
+
+int ftgemm_batched_config(ftgemm_t h, int p, ftgemm_config_t* config) {
+    if (!h || !config || !h->plan_valid || p < 0 || p >= (int)h->plan_cfg.size()) return FTGEMM_INVALID;
+    *config = h->plan_cfg[(size_t)p];
+    return FTGEMM_OK;
+}
+
+int ftgemm_get_tuned(ftgemm_t h, ftgemm_tuned_t* out, int cap, int* n) {
+    if (!h || cap < 0 || (cap > 0 && !out)) return FTGEMM_INVALID;
+    const int cnt = (int)h->tuned.size();
+    for (int i = 0; i < std::min(cap, cnt); ++i) out[i] = h->tuned[(size_t)i];
+    if (n) *n = cnt;
+    return FTGEMM_OK;
+}
+
+int ftgemm_add_tuned(ftgemm_t h, const ftgemm_tuned_t* e) {
+    if (!h || !e || e->ft_level < 0 || e->ft_level > 2 || e->config.check_interval < 1) return FTGEMM_INVALID;
+    if (find_variant(h->dtype, e->config) < 0) return FTGEMM_UNSUPPORTED;
+    for (ftgemm_tuned_t& t : h->tuned)
+        if (t.m == e->m && t.n == e->n && t.k == e->k && t.ft_level == e->ft_level) {
+            t.config = e->config;
+            return FTGEMM_OK;
+        }
+    h->tuned.push_back(*e);
+    return FTGEMM_OK;
+}
+
+int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int max_k_between_checks,
+                hipStream_t stream, ftgemm_config_t* best) {
+    if (!h || ftgemm_validate(m, n, k, std::max<int64_t>(1, m), std::max<int64_t>(1, k), std::max<int64_t>(1, m),
+                              ft_level, 0.f, nullptr) != FTGEMM_OK || m == 0 || n == 0 || k == 0 ||
+        max_k_between_checks < 0)
+        return FTGEMM_INVALID;
+    if (!dtype_supported(h->dtype)) return FTGEMM_UNSUPPORTED;
+    const int kmax = max_k_between_checks > 0 ? max_k_between_checks : 256;
+    const size_t esz = h->dtype == FTGEMM_F32 ? 4 : h->dtype == FTGEMM_BF16 ? 2 : 1;
+    DeviceGuard g(h->device);
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = FTGEMM_OK;
+    ftgemm_config_t pick{};
+    float pick_ms = 0.f;
+    const bool was_forced = h->forced;
+    const ftgemm_config_t was_cfg = h->cfg;
+    if (hipMalloc(&A, esz * (size_t)m * (size_t)k) != hipSuccess || hipMalloc(&B, esz * (size_t)k * (size_t)n) != hipSuccess ||
+        hipMalloc(&C, 4 * (size_t)m * (size_t)n) != hipSuccess) {
+        st = FTGEMM_NO_MEMORY;
+    } else if (hipMemsetAsync(A, 0, esz * (size_t)m * (size_t)k, stream) != hipSuccess ||
+               hipMemsetAsync(B, 0, esz * (size_t)k * (size_t)n, stream) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = FTGEMM_HIP_ERROR;
+    } else {
+        const int nv = variant_count(h->dtype);
+        for (int v = 0; v < nv && st == FTGEMM_OK; ++v) {
+            const Variant x = variant_at(h->dtype, v);
+            const int64_t nk = (k + x.k_step - 1) / x.k_step;
+            for (int gi = 1; st == FTGEMM_OK; gi *= 2) {
+                if (gi > 1 && ((int64_t)gi * x.k_step > kmax || gi > nk)) break;
+                if (ft_level != 2 && gi > 1) break;   // the interval only matters for online checks
+                h->cfg = {x.m_tile, x.n_tile, x.k_step, gi};
+                h->forced = true;
+                auto once = [&]() {
+                    return ftgemm_run(h, m, n, k, 1.0f, A, std::max<int64_t>(1, m), B, std::max<int64_t>(1, k), 0.0f,
+                                      static_cast<float*>(C), std::max<int64_t>(1, m), ft_level, 0.f, stream, nullptr);
+                };
+                if (once() != FTGEMM_OK) { st = FTGEMM_HIP_ERROR; break; }   // warm-up
+                const int reps = 3;
+                if (hipEventRecord(e0, stream) != hipSuccess) { st = FTGEMM_HIP_ERROR; break; }
+                for (int r = 0; r < reps; ++r) once();
+                float ms = 0.f;
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = FTGEMM_HIP_ERROR; break; }
+                if (pick.m_tile == 0 || ms < pick_ms) {
+                    pick = h->cfg;
+                    pick_ms = ms;
+                }
+            }
+        }
+    }
+    h->forced = was_forced;
+    h->cfg = was_cfg;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(stream);
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    if (C) (void)hipFree(C);
+    if (st != FTGEMM_OK) return st;
+    ftgemm_tuned_t e{m, n, k, ft_level, pick};
+    ftgemm_add_tuned(h, &e);
+    if (best) *best = pick;
+    return FTGEMM_OK;
+}
+
+int ftgemm_tune_batched(ftgemm_t h, hipStream_t stream, double* rates) {
+    if (!h) return FTGEMM_INVALID;
+    DeviceGuard g(h->device);
+    constexpr int kProbs = 64, kDim = 512;
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = FTGEMM_OK;
+    const size_t ab = 4 * (size_t)kDim * kDim, cb = 4 * (size_t)kDim * kDim;
+    double measured[kBatchVariants] = {0, 0, 0};
+    const bool had_plan = h->plan_valid;
+    if (hipMalloc(&A, ab * kProbs) != hipSuccess || hipMalloc(&B, ab * kProbs) != hipSuccess ||
+        hipMalloc(&C, cb * kProbs) != hipSuccess) {
+        st = FTGEMM_NO_MEMORY;
+    } else if (hipMemsetAsync(A, 0, ab * kProbs, stream) != hipSuccess || hipMemsetAsync(B, 0, ab * kProbs, stream) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = FTGEMM_HIP_ERROR;
+    } else {
+        // each variant alone: force it by giving the model a single admissible rate
+        const double saved[kBatchVariants] = {h->batch_rate[0], h->batch_rate[1], h->batch_rate[2]};
+        for (int v = 0; v < kBatchVariants && st == FTGEMM_OK; ++v) {
+            for (int u = 0; u < kBatchVariants; ++u) h->batch_rate[u] = (u == v) ? 1.0 : 1e-30;
+            std::vector<ftgemm_problem_t> probs(kProbs);
+            for (int p = 0; p < kProbs; ++p) {
+                ftgemm_problem_t& q = probs[(size_t)p];
+                std::memset(&q, 0, sizeof(q));
+                q.dtype = batch_variant_dtype(v);
+                q.m = q.n = q.k = kDim;
+                q.lda = q.ldb = q.ldc = kDim;
+                q.alpha = 1.f;
+                q.beta = 0.f;
+                q.scale_a = q.scale_b = 1.f;
+                q.A = static_cast<char*>(A) + ab * p;
+                q.B = static_cast<char*>(B) + ab * p;
+                q.C = reinterpret_cast<float*>(static_cast<char*>(C) + cb * p);
+            }
+            h->plan_valid = false;
+            if (ftgemm_batched(h, kProbs, probs.data(), 2, 0.f, stream, nullptr) != FTGEMM_OK) {
+                st = FTGEMM_HIP_ERROR;
+                break;
+            }
+            float ms = 0.f;
+            const int reps = 5;
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = FTGEMM_HIP_ERROR; break; }
+            for (int r = 0; r < reps; ++r) ftgemm_batched(h, kProbs, probs.data(), 2, 0.f, stream, nullptr);
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f)) { st = FTGEMM_HIP_ERROR; break; }
+            measured[v] = (double)kProbs * kDim * kDim * kDim * reps / (ms * 1e-3);
+        }
+        for (int u = 0; u < kBatchVariants; ++u) h->batch_rate[u] = st == FTGEMM_OK ? measured[u] : saved[u];
+    }
+    (void)had_plan;
+    h->plan_valid = false;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(stream);
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    if (C) (void)hipFree(C);
+    if (st == FTGEMM_OK && rates)
+        for (int u = 0; u < kBatchVariants; ++u) rates[u] = measured[u];
+    return st;
 }
 
 }  // extern "C"

@@ -1,296 +1,15 @@
-// ftgemm_bf16.hip -- BF16-input online ABFT GEMM kernels for gfx950 (MI355X).
-//
-// C = alpha * (scale_a * A) (scale_b * B) + beta * C with A, B in bfloat16 and
-// FP32 accumulation on v_mfma_f32_32x32x16_bf16.  The fault tolerance is the
-// same threadblock-level online ABFT as the FP32 kernels (section 2.2 Eq. 1-4,
-// section 4.2.3): every bf16 value decodes exactly to FP32, so the encodings
-// e^T A and B e, the reference checksums, the norms and the check all run in
-// FP32 on the decoded operands, with the FP32 roundoff threshold.  The
-// per-tensor scales are powers of two applied in the epilogue, outside the
-// checked region.
-//
-// Layout: both operands sit in LDS k-contiguous ([row][k], 16-byte padded
-// rows), which is what a 32x32x16 MFMA operand wants: lane l supplies 8
-// consecutive k of one row.  B (column-major K x N) is k-contiguous already;
-// A (column-major M x K) is i-contiguous, so each thread loads an 8-row x
-// 4-k block and transposes it in registers (v_perm_b32) on the way to LDS.
-// As in the FP32 kernels the MFMA computes P^T = B^T A^T, so lane l % 32 owns
-// one row of C.
-#include "ftgemm_abft.hpp"
+// ftgemm_bf16.hip -- kernel entry points and variant table of the BF16 kernels
+// (the tile computation is in ftgemm_bf16.hpp).
+#include "ftgemm_bf16.hpp"
 
 namespace ftgemm_impl {
 namespace {
 
-using namespace abft;
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-
-template <int BM, int BN, int BK>
-struct OperandsBF16 {
-    static constexpr int KP = BK + 8;          // row pitch in bf16 (16 B of padding)
-    unsigned short As[2][BM][KP];              // A panel, i-major, k contiguous
-    unsigned short Bs[2][BN][KP];              // B panel, j-major, k contiguous
-    float wsum[3][BK];                         // e^T A per k (accumulated across waves, 3 rotating slots)
-    float vsum[3][BK];                         // B e per k (same)
-    float dummy[64];
-};
-
-template <int BM, int BN, int BK, int WM, int WN>
-struct SmemBF16 {
-    OperandsBF16<BM, BN, BK> op;
-    CheckLds<Geometry<BM, BN, WM, WN>> ck;
-};
-
-// bf16 halves of a packed dword, exactly as FP32
-__device__ __forceinline__ float bf_lo(unsigned x) { return __uint_as_float(x << 16); }
-__device__ __forceinline__ float bf_hi(unsigned x) { return __uint_as_float(x & 0xffff0000u); }
-
 template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
 __global__ __launch_bounds__(64 * WM * WN) void ftgemm_bf16_kernel(LaunchArgs a) {
-    using G = Geometry<BM, BN, WM, WN>;
-    constexpr int NT = G::NT, TM = G::TM, TN = G::TN, MI = G::MI, NI = G::NI;
-    constexpr int KP = OperandsBF16<BM, BN, BK>::KP;
-    // A: an 8-row x 4-k block per thread; B: 16-byte k-chunks (8 k of a column)
-    constexpr int AKQ = BK / 4;                 // k-quads per panel
-    constexpr int BKC = BK / 8;                 // k-chunks per column
-    constexpr int NB = BN * BKC / NT;           // B chunks per thread
-    static_assert(G::SPLIT, "the bf16 kernel assumes one owned row or column per thread");
-    static_assert(BM / 8 * AKQ == NT, "one A block per thread");
-    static_assert(NB >= 1 && NT % BKC == 0 && BK % 16 == 0, "B chunk mapping");
-    static_assert(AKQ == 16 && BKC == 8, "encode lane mapping assumes BK = 64");
-
-    __shared__ SmemBF16<BM, BN, BK, WM, WN> sm;
-    OperandsBF16<BM, BN, BK>& op = sm.op;
-
+    __shared__ bf16::SmemBF16<BM, BN, BK, WM, WN> sm;
     const int ntm = (a.M + BM - 1) / BM;
-    const Thread th = make_thread<G>(a, blockIdx.x % ntm, blockIdx.x / ntm);
-    const int tid = th.tid, lane = th.lane, wm = th.wm, wn = th.wn, l32 = th.l32, hh = th.hh;
-    const int mI = th.mI, nJ = th.nJ;
-    const int nk = (a.K + BK - 1) / BK;
-    const unsigned short* A = static_cast<const unsigned short*>(static_cast<const void*>(a.A));
-    const unsigned short* B = static_cast<const unsigned short*>(static_cast<const void*>(a.B));
-
-    const bool alignA = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && ((a.lda & 7) == 0);
-    const bool alignB = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && ((a.ldb & 7) == 0);
-
-    if constexpr (FT > 0) {
-        for (int x = tid; x < 3 * BK; x += NT) {
-            (&op.wsum[0][0])[x] = 0.f;
-            (&op.vsum[0][0])[x] = 0.f;
-        }
-    }
-    int fnext = 0, flogged = 0;
-    if constexpr (INJ) gather_faults<G>(sm.ck, a, th);
-    __syncthreads();
-
-    // ---- global -> register staging ----
-    const int akq = tid % AKQ, ac = tid / AKQ;     // A block: rows 8ac.., k 4akq..
-    u32x4 ra[4];                                    // 4 k-columns x 8 rows (bf16 pairs)
-    u32x4 rb[NB];                                   // 8 k of one column each
-    const unsigned short* Abase = A + th.i0;
-    const unsigned short* Bbase = B + (size_t)th.j0 * a.ldb;
-
-    auto load_panels = [&](int t) {
-        const int k0 = t * BK;
-        const bool fullk = k0 + BK <= a.K;
-        if (alignA && fullk && mI == BM) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                ra[e] = *reinterpret_cast<const u32x4*>(Abase + (size_t)(k0 + 4 * akq + e) * a.lda + 8 * ac);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gk = k0 + 4 * akq + e, gi = 8 * ac;
-                const unsigned short* p = Abase + (size_t)gk * a.lda + gi;
-                unsigned v[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const bool in = gk < a.K && gi + q < mI;
-                    const unsigned x = *(in ? p + q : A);
-                    v[q] = in ? x : 0u;
-                }
-#pragma unroll
-                for (int d = 0; d < 4; ++d) ra[e][d] = v[2 * d] | (v[2 * d + 1] << 16);
-            }
-        }
-        if (alignB && fullk && nJ == BN) {
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
-                const int kc = f % BKC, jj = f / BKC;
-                rb[r] = *reinterpret_cast<const u32x4*>(Bbase + (size_t)jj * a.ldb + k0 + 8 * kc);
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
-                const int kc = f % BKC, jj = f / BKC;
-                const int gk = k0 + 8 * kc;
-                const unsigned short* p = Bbase + (size_t)jj * a.ldb + gk;
-                unsigned v[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const bool in = jj < nJ && gk + q < a.K;
-                    const unsigned x = *(in ? p + q : B);
-                    v[q] = in ? x : 0u;
-                }
-#pragma unroll
-                for (int d = 0; d < 4; ++d) rb[r][d] = v[2 * d] | (v[2 * d + 1] << 16);
-            }
-        }
-    };
-
-    // registers -> LDS (A transposed to k-contiguous rows), fused with the
-    // encodings e^T A and B e in FP32 (section 2.2, Eq. 1-2)
-    auto store_panels = [&](int buf, int slot) {
-        // A: column e of the thread's block holds rows 8ac..8ac+7 as bf16
-        // pairs; row r gathers element r of columns 0..3 into 8 bytes.
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int d = r >> 1;
-            const unsigned sel = (r & 1) ? 0x07060302u : 0x05040100u;   // high or low halves
-            u32x2 w;
-            w[0] = __builtin_amdgcn_perm(ra[1][d], ra[0][d], sel);
-            w[1] = __builtin_amdgcn_perm(ra[3][d], ra[2][d], sel);
-            *reinterpret_cast<u32x2*>(&op.As[buf][8 * ac + r][4 * akq]) = w;
-        }
-#pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            const int f = tid + NT * r;
-            const int kc = f % BKC, jj = f / BKC;
-            *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][8 * kc]) = rb[r];
-        }
-        if constexpr (FT > 0) {
-            // e^T A for the thread's 4 k over its 8 rows, then over the 32
-            // threads of the same k-quad: lane bits 4, 5 in-wave (reduce-
-            // scatter leaves k = 4 akq + ((lane >> 4) & 3)), waves in LDS.
-            float ws[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float x = 0.f;
-#pragma unroll
-                for (int d = 0; d < 4; ++d) x += bf_lo(ra[e][d]) + bf_hi(ra[e][d]);
-                ws[e] = x;
-            }
-            ReduceScatter<4, 5, 4>::run(ws, lane);
-            atomicAdd(&op.wsum[slot][4 * akq + ((lane >> 4) & 3)], ws[0]);
-            // B e for the thread's 8 k over its NB columns, then over the
-            // lanes of the same k-chunk (bits 3..5): lane keeps
-            // k = 8 kc + ((lane >> 3) & 7); waves add in LDS.
-            float vs[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) vs[q] = 0.f;
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    vs[2 * d] += bf_lo(rb[r][d]);
-                    vs[2 * d + 1] += bf_hi(rb[r][d]);
-                }
-            ReduceScatter<8, 5, 3>::run(vs, lane);
-            atomicAdd(&op.vsum[slot][8 * (tid % BKC) + ((lane >> 3) & 7)], vs[0]);
-        }
-    };
-
-    Acc<G> acc;
-#pragma unroll
-    for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < NI; ++bj)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0.0f;
-
-    // owned checksum vector: a row of A (with B e) or a column of B (with
-    // e^T A); both are k-contiguous rows of the LDS panels
-    float ck0 = 0.f, nq0 = 0.f;
-    float& Rr = ck0;
-    float& na2 = nq0;
-    float& Sc = ck0;
-    float& nb2 = nq0;
-    const bool row_role = th.row_role;
-    const int own = row_role ? min(tid, BM - 1) : min(max(tid - G::COL0, 0), BN - 1);
-    const unsigned short* const x_arr = row_role ? &op.As[0][0][0] : &op.Bs[0][0][0];
-    constexpr int XBUF = BM * KP;   // == BN * KP (square tiles)
-    static_assert(BM == BN, "owner addressing assumes square tiles");
-
-    // one k16 sub-step: an MFMA on every block of the wave tile
-    auto mfma_sub = [&](int cur, int s) {
-        bf16x8 bx[NI], ay[MI];
-#pragma unroll
-        for (int bj = 0; bj < NI; ++bj)
-            bx[bj] = *reinterpret_cast<const bf16x8*>(&op.Bs[cur][wn * TN + 32 * bj + l32][16 * s + 8 * hh]);
-#pragma unroll
-        for (int bi = 0; bi < MI; ++bi)
-            ay[bi] = *reinterpret_cast<const bf16x8*>(&op.As[cur][wm * TM + 32 * bi + l32][16 * s + 8 * hh]);
-#pragma unroll
-        for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < NI; ++bj)
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bx[bj], ay[bi], acc[bi][bj], 0, 0, 0);
-    };
-
-    // reference checksum update (Eq. 4) for the same 16 k
-    auto ft_sub = [&](int cur, int slot, int s) {
-        const unsigned short* px = x_arr + cur * XBUF + own * KP + 16 * s;
-        const float* py = row_role ? &op.vsum[slot][16 * s] : &op.wsum[slot][16 * s];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const u32x4 xv = *reinterpret_cast<const u32x4*>(px + 8 * h);
-            const f32x4 y0 = *reinterpret_cast<const f32x4*>(py + 8 * h);
-            const f32x4 y1 = *reinterpret_cast<const f32x4*>(py + 8 * h + 4);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const float lo = bf_lo(xv[d]), hi = bf_hi(xv[d]);
-                const float ylo = d < 2 ? y0[2 * d] : y1[2 * d - 4];
-                const float yhi = d < 2 ? y0[2 * d + 1] : y1[2 * d - 3];
-                ck0 = fmaf(lo, ylo, ck0);
-                ck0 = fmaf(hi, yhi, ck0);
-                nq0 = fmaf(lo, lo, nq0);
-                nq0 = fmaf(hi, hi, nq0);
-            }
-        }
-    };
-
-    auto step = [&](int t, auto has_next) {
-        constexpr bool NEXT = decltype(has_next)::value;
-        const int cur = t & 1;
-        if constexpr (NEXT) load_panels(t + 1);
-        if constexpr (FT > 0 && NEXT) {   // slot for step t+2: its last reader finished before this step
-            const int x = tid < BK ? tid : BK - 1;
-            op.wsum[(t + 2) % 3][x] = 0.f;
-            op.vsum[(t + 2) % 3][x] = 0.f;
-        }
-#pragma unroll
-        for (int s = 0; s < BK / 16; ++s) {
-            mfma_sub(cur, s);
-            if constexpr (FT > 0) ft_sub(cur, t % 3, s);
-            if constexpr (NEXT) {
-                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3);
-            }
-        }
-    };
-
-    auto post = [&](int t) -> bool {
-        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
-        bool do_check = false;
-        if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
-        if constexpr (FT == 1) do_check = (t == nk - 1);
-        if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
-        return do_check;
-    };
-
-    load_panels(0);
-    store_panels(0, 0);
-    __syncthreads();
-    for (int t = 0; t + 1 < nk; ++t) {
-        step(t, std::true_type{});
-        if (!post(t)) __syncthreads();
-    }
-    step(nk - 1, std::false_type{});
-    post(nk - 1);
-    epilogue<G>(acc, a, th, a.scale);
+    bf16::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
 }
 
 template <int BM, int BN, int BK, int WM, int WN>

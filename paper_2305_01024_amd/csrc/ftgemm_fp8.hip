@@ -1,0 +1,57 @@
+// ftgemm_fp8.hip -- kernel entry points and variant table of the FP8 kernels
+// (the tile computation is in ftgemm_fp8.hpp).
+#include "ftgemm_fp8.hpp"
+
+namespace ftgemm_impl {
+namespace {
+
+template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
+__global__ __launch_bounds__(64 * WM * WN) void ftgemm_fp8_kernel(LaunchArgs a) {
+    __shared__ fp8::SmemFP8<BM, BN, BK, WM, WN> sm;
+    const int ntm = (a.M + BM - 1) / BM;
+    fp8::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_shape_fp8(bool inject, const LaunchArgs& a, hipStream_t s) {
+    const int ntm = (a.M + BM - 1) / BM, ntn = (a.N + BN - 1) / BN;
+    const dim3 grid((unsigned)(ntm * ntn)), block(64 * WM * WN);
+#define FTGEMM_LAUNCH(FTL, INJL) \
+    hipLaunchKernelGGL((ftgemm_fp8_kernel<BM, BN, BK, WM, WN, FTL, INJL>), grid, block, 0, s, a)
+    if (inject) {
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, true);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, true);
+        else FTGEMM_LAUNCH(2, true);
+    } else {
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, false);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, false);
+        else FTGEMM_LAUNCH(2, false);
+    }
+#undef FTGEMM_LAUNCH
+    return hipGetLastError();
+}
+
+constexpr Variant kVariantsFP8[] = {
+    {256, 256, 64},
+};
+
+}  // namespace
+
+int fp8_variant_count() { return sizeof(kVariantsFP8) / sizeof(kVariantsFP8[0]); }
+Variant fp8_variant(int idx) { return kVariantsFP8[idx]; }
+int fp8_find_variant(int m_tile, int n_tile, int k_step) {
+    for (int v = 0; v < fp8_variant_count(); ++v) {
+        const Variant& x = kVariantsFP8[v];
+        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step) return v;
+    }
+    return -1;
+}
+
+hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t s) {
+    switch (idx) {
+        case 0: return launch_shape_fp8<256, 256, 64, 2, 4>(inject, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ftgemm_impl

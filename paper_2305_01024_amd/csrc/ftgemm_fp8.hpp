@@ -1,0 +1,302 @@
+// ftgemm_fp8.hpp -- FP8 (OCP E4M3) input online ABFT GEMM kernels for gfx950.
+//
+// C = alpha * (scale_a * A) (scale_b * B) + beta * C with A, B as E4M3 codes
+// and FP32 accumulation on v_mfma_f32_32x32x16_fp8_fp8.  The fault tolerance
+// is the threadblock-level online ABFT of the FP32 kernels (section 2.2
+// Eq. 1-4, section 4.2.3): every E4M3 value converts exactly to FP32
+// (v_cvt_pk_f32_fp8), so the encodings e^T A and B e, the reference
+// checksums, the norms and the check run in FP32 on the decoded operands with
+// the FP32 roundoff threshold.  The per-tensor scales are applied in the
+// epilogue, outside the checked region.
+//
+// Layout: both operands sit in LDS k-contiguous ([row][k], 16-byte padded
+// rows): lane l of a 32x32x16 MFMA supplies 8 consecutive k (8 bytes) of one
+// row.  B (column-major K x N) is k-contiguous already; A (column-major
+// M x K) is i-contiguous, so each thread loads an 8-row x 4-k byte block
+// (four 8-byte loads) and transposes it in registers on the way to LDS.  As
+// in the other kernels the MFMA computes P^T = B^T A^T, so lane l % 32 owns
+// one row of C.
+#pragma once
+
+#include "ftgemm_abft.hpp"
+
+namespace ftgemm_impl {
+namespace fp8 {
+
+using namespace abft;
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <int BM, int BN, int BK>
+struct alignas(16) OperandsFP8 {   // 16-byte aligned: the panel reads are 16-byte LDS loads
+    static constexpr int KP = BK + 16;         // row pitch in bytes (16 B of padding)
+    unsigned char As[2][BM][KP];               // A panel, i-major, k contiguous
+    unsigned char Bs[2][BN][KP];               // B panel, j-major, k contiguous
+    float wsum[2][BK];                         // e^T A per k
+    float vsum[3][BK];                         // B e per k (accumulated across waves, 3 rotating slots)
+    float dummy[64];
+};
+
+template <int BM, int BN, int BK, int WM, int WN>
+struct SmemFP8 {
+    OperandsFP8<BM, BN, BK> op;
+    CheckLds<Geometry<BM, BN, WM, WN>> ck;
+};
+
+// the four E4M3 values of a dword, exactly as FP32 (byte q -> element q)
+__device__ __forceinline__ void decode4(unsigned x, float* f) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, false);
+    const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, true);
+    f[0] = lo[0];
+    f[1] = lo[1];
+    f[2] = hi[0];
+    f[3] = hi[1];
+}
+
+// One BM x BN output tile (tm, tn) of the problem in `a`, computed by one
+// workgroup of 64 * WM * WN threads with `sm` as its LDS.
+template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
+__device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP8<BM, BN, BK, WM, WN>& sm) {
+    using G = Geometry<BM, BN, WM, WN>;
+    constexpr int NT = G::NT, TM = G::TM, TN = G::TN, MI = G::MI, NI = G::NI;
+    constexpr int KP = OperandsFP8<BM, BN, BK>::KP;
+    // A: an 8-row x 4-k block per thread (rows 8 ac.., k 4 akq..), with the
+    // 32 lanes of one k-quad covering 256 contiguous rows.  B: 16-byte
+    // k-chunks (16 k of one column).
+    constexpr int ARB = BM / 8;                 // row blocks of the A panel
+    constexpr int AKQ = BK / 4;                 // k-quads per panel
+    constexpr int BKC = BK / 16;                // k-chunks per column
+    constexpr int NB = BN * BKC / NT;           // B chunks per thread
+    static_assert(G::SPLIT, "the fp8 kernel assumes one owned row or column per thread");
+    static_assert(ARB * AKQ == NT && ARB == 32, "one A block per thread, 32 lanes per k-quad");
+    static_assert(NB >= 1 && NT % BKC == 0 && BK % 16 == 0 && BKC == 4, "B chunk mapping");
+    static_assert(BM == BN, "owner addressing assumes square tiles");
+
+    OperandsFP8<BM, BN, BK>& op = sm.op;
+
+    const Thread th = make_thread<G>(a, tm, tn);
+    const int tid = th.tid, lane = th.lane, wm = th.wm, wn = th.wn, l32 = th.l32, hh = th.hh;
+    const int mI = th.mI, nJ = th.nJ;
+    const int nk = (a.K + BK - 1) / BK;
+    const unsigned char* A = static_cast<const unsigned char*>(static_cast<const void*>(a.A));
+    const unsigned char* B = static_cast<const unsigned char*>(static_cast<const void*>(a.B));
+
+    const bool alignA = ((reinterpret_cast<uintptr_t>(A) & 7) == 0) && ((a.lda & 7) == 0);
+    const bool alignB = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && ((a.ldb & 15) == 0);
+
+    if constexpr (FT > 0) {
+        for (int x = tid; x < 3 * BK; x += NT) (&op.vsum[0][0])[x] = 0.f;
+    }
+    int fnext = 0, flogged = 0;
+    if constexpr (INJ) gather_faults<G>(sm.ck, a, th);
+    __syncthreads();
+
+    // ---- global -> register staging ----
+    const int ac = tid % ARB, akq = tid / ARB;     // A block: rows 8 ac.., k 4 akq..
+    u32x2 ra[4];                                    // 4 k-columns x 8 rows (bytes)
+    u32x4 rb[NB];                                   // 16 k of one column each
+    const unsigned char* Abase = A + th.i0;
+    const unsigned char* Bbase = B + (size_t)th.j0 * a.ldb;
+
+    auto load_panels = [&](int t) {
+        const int k0 = t * BK;
+        const bool fullk = k0 + BK <= a.K;
+        if (alignA && fullk && mI == BM) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                ra[e] = *reinterpret_cast<const u32x2*>(Abase + (size_t)(k0 + 4 * akq + e) * a.lda + 8 * ac);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gk = k0 + 4 * akq + e, gi = 8 * ac;
+                const unsigned char* p = Abase + (size_t)gk * a.lda + gi;
+                unsigned v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool in = gk < a.K && gi + q < mI;
+                    const unsigned x = *(in ? p + q : A);
+                    v[q] = in ? x : 0u;
+                }
+                ra[e][0] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+                ra[e][1] = v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24);
+            }
+        }
+        if (alignB && fullk && nJ == BN) {
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const int f = tid + NT * r;
+                const int kc = f % BKC, jj = f / BKC;
+                rb[r] = *reinterpret_cast<const u32x4*>(Bbase + (size_t)jj * a.ldb + k0 + 16 * kc);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const int f = tid + NT * r;
+                const int kc = f % BKC, jj = f / BKC;
+                const int gk = k0 + 16 * kc;
+                const unsigned char* p = Bbase + (size_t)jj * a.ldb + gk;
+                unsigned v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const bool in = jj < nJ && gk + q < a.K;
+                    const unsigned x = *(in ? p + q : B);
+                    v[q] = in ? x : 0u;
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    rb[r][d] = v[4 * d] | (v[4 * d + 1] << 8) | (v[4 * d + 2] << 16) | (v[4 * d + 3] << 24);
+            }
+        }
+    };
+
+    // registers -> LDS (A transposed to k-contiguous rows), fused with the
+    // encodings e^T A and B e in FP32 (section 2.2, Eq. 1-2)
+    auto store_panels = [&](int buf, int slot) {
+        // column e of the block holds rows 8 ac .. 8 ac + 7 as bytes; row r
+        // gathers byte r of the 4 columns into one dword (k 4 akq .. +3).
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int d = r >> 2, sh = 8 * (r & 3);
+            const unsigned w = ((ra[0][d] >> sh) & 0xffu) | (((ra[1][d] >> sh) & 0xffu) << 8) |
+                               (((ra[2][d] >> sh) & 0xffu) << 16) | (((ra[3][d] >> sh) & 0xffu) << 24);
+            *reinterpret_cast<unsigned*>(&op.As[buf][8 * ac + r][4 * akq]) = w;
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int f = tid + NT * r;
+            const int kc = f % BKC, jj = f / BKC;
+            *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][16 * kc]) = rb[r];
+        }
+        if constexpr (FT > 0) {
+            // e^T A for the thread's 4 k over its 8 rows, then over the 32
+            // lanes of the same k-quad (bits 0..4): the reduce-scatter leaves
+            // k = 4 akq + ((lane >> 3) & 3), stored by lanes with (lane & 7) == 0.
+            float ws[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float f0[4], f1[4];
+                decode4(ra[e][0], f0);
+                decode4(ra[e][1], f1);
+                ws[e] = ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f1[0] + f1[1]) + (f1[2] + f1[3]));
+            }
+            ReduceScatter<4, 4, 0>::run(ws, lane);
+            {
+                float* dst = ((lane & 7) == 0) ? &op.wsum[buf][4 * akq + ((lane >> 3) & 3)] : &op.dummy[lane];
+                *dst = ws[0];
+            }
+            // B e for the thread's 16 k over its NB columns, then over the
+            // lanes of the same k-chunk (bits 2..5): lane keeps
+            // k = 16 kc + ((lane >> 2) & 15); waves add in LDS.
+            float vs[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) vs[q] = 0.f;
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    float f[4];
+                    decode4(rb[r][d], f);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) vs[4 * d + q] += f[q];
+                }
+            ReduceScatter<16, 5, 2>::run(vs, lane);
+            atomicAdd(&op.vsum[slot][16 * (tid % BKC) + ((lane >> 2) & 15)], vs[0]);
+        }
+    };
+
+    Acc<G> acc;
+#pragma unroll
+    for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NI; ++bj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0.0f;
+
+    // owned checksum vector: a row of A (with B e) or a column of B (with
+    // e^T A); both are k-contiguous rows of the LDS panels
+    float ck0 = 0.f, nq0 = 0.f;
+    float& Rr = ck0;
+    float& na2 = nq0;
+    float& Sc = ck0;
+    float& nb2 = nq0;
+    const bool row_role = th.row_role;
+    const int own = row_role ? min(tid, BM - 1) : min(max(tid - G::COL0, 0), BN - 1);
+    const unsigned char* const x_arr = row_role ? &op.As[0][0][0] : &op.Bs[0][0][0];
+    constexpr int XBUF = BM * KP;   // == BN * KP
+
+    // one k16 sub-step: an MFMA on every block of the wave tile
+    auto mfma_sub = [&](int cur, int s) {
+        long bx[NI], ay[MI];
+#pragma unroll
+        for (int bj = 0; bj < NI; ++bj)
+            bx[bj] = *reinterpret_cast<const long*>(&op.Bs[cur][wn * TN + 32 * bj + l32][16 * s + 8 * hh]);
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+            ay[bi] = *reinterpret_cast<const long*>(&op.As[cur][wm * TM + 32 * bi + l32][16 * s + 8 * hh]);
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NI; ++bj)
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(bx[bj], ay[bi], acc[bi][bj], 0, 0, 0);
+    };
+
+    // reference checksum update (Eq. 4) for the same 16 k
+    auto ft_sub = [&](int cur, int slot, int s) {
+        const unsigned char* px = x_arr + cur * XBUF + own * KP + 16 * s;
+        const float* py = row_role ? &op.vsum[slot][16 * s] : &op.wsum[cur][16 * s];
+        const u32x4 xv = *reinterpret_cast<const u32x4*>(px);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const f32x4 y = *reinterpret_cast<const f32x4*>(py + 4 * d);
+            float x[4];
+            decode4(xv[d], x);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ck0 = fmaf(x[q], y[q], ck0);
+                nq0 = fmaf(x[q], x[q], nq0);
+            }
+        }
+    };
+
+    auto step = [&](int t, auto has_next) {
+        constexpr bool NEXT = decltype(has_next)::value;
+        const int cur = t & 1;
+        if constexpr (NEXT) load_panels(t + 1);
+        if constexpr (FT > 0 && NEXT) {   // slot for step t+2: its last reader finished before this step
+            (&op.vsum[(t + 2) % 3][0])[tid < BK ? tid : BK - 1] = 0.f;
+        }
+#pragma unroll
+        for (int s = 0; s < BK / 16; ++s) {
+            mfma_sub(cur, s);
+            if constexpr (FT > 0) ft_sub(cur, t % 3, s);
+            if constexpr (NEXT) {
+                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3);
+            }
+        }
+    };
+
+    auto post = [&](int t) -> bool {
+        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
+        bool do_check = false;
+        if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
+        if constexpr (FT == 1) do_check = (t == nk - 1);
+        if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
+        return do_check;
+    };
+
+    load_panels(0);
+    store_panels(0, 0);
+    __syncthreads();
+    for (int t = 0; t + 1 < nk; ++t) {
+        step(t, std::true_type{});
+        if (!post(t)) __syncthreads();
+    }
+    step(nk - 1, std::false_type{});
+    post(nk - 1);
+    epilogue<G>(acc, a, th, a.scale);
+}
+
+}  // namespace fp8
+}  // namespace ftgemm_impl

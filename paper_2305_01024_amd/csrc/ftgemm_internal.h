@@ -1,5 +1,6 @@
 // ftgemm_internal.h -- launch interface between the C ABI (ftgemm_api.cpp)
-// and the gfx950 kernels (ftgemm_fp32.hip).  Not installed, not part of the ABI.
+// and the gfx950 kernels (ftgemm_fp32.hip, ftgemm_bf16.hip, ftgemm_fp8.hip).
+// Not installed, not part of the ABI.
 #pragma once
 
 #include <stdint.h>
@@ -61,6 +62,56 @@ int bf16_variant_count();
 Variant bf16_variant(int idx);
 int bf16_find_variant(int m_tile, int n_tile, int k_step);
 hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+
+// Kernel variants for FP8 E4M3 operands (A, B as 8-bit codes).
+int fp8_variant_count();
+Variant fp8_variant(int idx);
+int fp8_find_variant(int m_tile, int n_tile, int k_step);
+hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+
+// ---- batched persistent launch ----
+// Device descriptor of one problem of a batched call.
+struct BatchProblem {
+    const void* A;
+    const void* B;
+    float* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t variant;             // batched tile variant, or -1: C = beta * C only (k == 0 or alpha == 0)
+    float alpha, beta, scale;
+    int32_t check_interval;      // in k-steps of the variant
+    int32_t ntm;                 // tiles along m
+    int32_t pad_;
+};
+
+// One work item: tile `tile` (tm + ntm * tn) of problem `problem`.
+struct BatchItem {
+    int32_t problem, tile;
+};
+
+struct BatchArgs {
+    const BatchProblem* probs;
+    const BatchItem* items;
+    int32_t n_items;
+    int32_t ft_level;
+    float tol_c;
+    int32_t event_cap;
+    ftgemm_event_t* events;
+    uint32_t* counters;
+    const ftgemm_fault_t* faults;    // injection build only
+    int32_t n_faults;
+    int32_t fault_log_cap;
+    ftgemm_fault_log_t* fault_log;
+};
+
+// Tile variants of the batched kernel (one 256-thread workgroup per tile):
+// 0 = FP32 128 x 128 x 32, 1 = FP32 64 x 64 x 64, 2 = BF16 128 x 128 x 64.
+constexpr int kBatchVariants = 3;
+Variant batch_variant(int v);
+int batch_variant_dtype(int v);
+// Workgroups of the batched kernel that are resident on the device at once.
+int batch_resident_blocks(int device);
+hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, hipStream_t stream);
 
 // C = beta * C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t stream);

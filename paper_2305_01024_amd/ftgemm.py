@@ -48,7 +48,18 @@ class Report(ctypes.Structure):
                 ("uncorrectable", ctypes.c_uint64), ("checksum_only", ctypes.c_uint64),
                 ("n_events", ctypes.c_uint32), ("cap_events", ctypes.c_uint32),
                 ("events", ctypes.c_void_p), ("config", Config), ("bad_arg", ctypes.c_int32),
-                ("tol_used", ctypes.c_float)]
+                ("tol_used", ctypes.c_float), ("bad_problem", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class Tuned(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("ft_level", ctypes.c_int64),
+                ("config", Config)]
+
+
+# ftgemm_problem_t: one problem of a batched call (96 bytes)
+PROBLEM_DTYPE = np.dtype([("dtype", "<i4"), ("reserved_", "<i4"), ("m", "<i8"), ("n", "<i8"), ("k", "<i8"),
+                          ("lda", "<i8"), ("ldb", "<i8"), ("ldc", "<i8"), ("alpha", "<f4"), ("beta", "<f4"),
+                          ("scale_a", "<f4"), ("scale_b", "<f4"), ("A", "<u8"), ("B", "<u8"), ("C", "<u8")])
 
 
 class ReportBuffer:
@@ -89,11 +100,18 @@ def lib():
                                  ctypes.POINTER(Report)]
         L.ftgemm_set_injection.argtypes = [vp, vp, i32]
         L.ftgemm_get_injection_log.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.ftgemm_batched.argtypes = [vp, i32, vp, i32, f32, vp, ctypes.POINTER(Report)]
+        L.ftgemm_batched_config.argtypes = [vp, i32, ctypes.POINTER(Config)]
+        L.ftgemm_tune.argtypes = [vp, i64, i64, i64, i32, i32, vp, ctypes.POINTER(Config)]
+        L.ftgemm_get_tuned.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.ftgemm_add_tuned.argtypes = [vp, ctypes.POINTER(Tuned)]
+        L.ftgemm_tune_batched.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.ftgemm_status_string.argtypes = [i32]
         L.ftgemm_status_string.restype = ctypes.c_char_p
         for name in ("ftgemm_create", "ftgemm_destroy", "ftgemm_set_scales", "ftgemm_set_config",
                      "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
-                     "ftgemm_get_injection_log"):
+                     "ftgemm_get_injection_log", "ftgemm_batched", "ftgemm_batched_config", "ftgemm_tune", "ftgemm_get_tuned",
+                     "ftgemm_add_tuned", "ftgemm_tune_batched"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -175,3 +193,76 @@ def ftgemm_get_injection_log(handle: int, cap: int = 16384) -> np.ndarray:
     _check(lib().ftgemm_get_injection_log(handle, out.ctypes.data, cap, ctypes.byref(n)),
            "ftgemm_get_injection_log")
     return out[: min(n.value, cap)].copy()
+
+
+def make_problems(count: int) -> np.ndarray:
+    """A zeroed array of `count` batched problem descriptors."""
+    return np.zeros(count, dtype=PROBLEM_DTYPE)
+
+
+def ftgemm_batched(handle: int, problems: np.ndarray, ft_level: int = FT_CORRECT, tol: float = 0.0,
+                   stream: int = 0, report: ReportBuffer | None = None) -> int:
+    """All problems of a PROBLEM_DTYPE array in one persistent launch.  Keep
+    `problems` unchanged between calls to reuse the handle's plan (required
+    under stream capture).  Returns the status (0 or 1); raises on errors."""
+    arr = np.ascontiguousarray(problems, dtype=PROBLEM_DTYPE)
+    st = lib().ftgemm_batched(handle, len(arr), arr.ctypes.data if len(arr) else None, ft_level, tol, stream,
+                              report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_batched")
+
+
+def ftgemm_batched_config(handle: int, p: int) -> Config:
+    """Configuration of problem p in the handle's current batched plan."""
+    c = Config()
+    _check(lib().ftgemm_batched_config(handle, p, ctypes.byref(c)), "ftgemm_batched_config")
+    return c
+
+
+def ftgemm_tune(handle: int, m: int, n: int, k: int, ft_level: int = FT_CORRECT, max_k_between_checks: int = 0,
+                stream: int = 0) -> Config:
+    """Time every tile variant and check interval on this shape; the fastest
+    is kept in the handle for later ftgemm_run calls and returned."""
+    c = Config()
+    _check(lib().ftgemm_tune(handle, m, n, k, ft_level, max_k_between_checks, stream, ctypes.byref(c)),
+           "ftgemm_tune")
+    return c
+
+
+def ftgemm_get_tuned(handle: int) -> list:
+    """The handle's tuned configurations as [(m, n, k, ft_level, (m_tile, n_tile, k_step, g))]."""
+    n = ctypes.c_int(0)
+    _check(lib().ftgemm_get_tuned(handle, None, 0, ctypes.byref(n)), "ftgemm_get_tuned")
+    buf = (Tuned * max(1, n.value))()
+    _check(lib().ftgemm_get_tuned(handle, buf, n.value, ctypes.byref(n)), "ftgemm_get_tuned")
+    return [(t.m, t.n, t.k, t.ft_level, t.config.as_tuple()) for t in buf[: n.value]]
+
+
+def ftgemm_add_tuned(handle: int, m: int, n: int, k: int, ft_level: int, config) -> None:
+    cfg = config if isinstance(config, Config) else Config(*config)
+    t = Tuned(m, n, k, ft_level, cfg)
+    _check(lib().ftgemm_add_tuned(handle, ctypes.byref(t)), "ftgemm_add_tuned")
+
+
+def save_tuned(handle: int, path: str) -> None:
+    """Persist the handle's tuned configurations as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump([{"m": m, "n": n, "k": k, "ft_level": lv, "config": list(c)}
+                   for (m, n, k, lv, c) in ftgemm_get_tuned(handle)], f, indent=1)
+
+
+def load_tuned(handle: int, path: str) -> int:
+    """Load tuned configurations written by save_tuned; returns how many."""
+    import json
+    with open(path) as f:
+        rows = json.load(f)
+    for r in rows:
+        ftgemm_add_tuned(handle, int(r["m"]), int(r["n"]), int(r["k"]), int(r["ft_level"]), tuple(r["config"]))
+    return len(rows)
+
+
+def ftgemm_tune_batched(handle: int, stream: int = 0) -> np.ndarray:
+    """Measure the batched tile variants' rates (multiply-adds per second)."""
+    rates = (ctypes.c_double * 3)()
+    _check(lib().ftgemm_tune_batched(handle, stream, rates), "ftgemm_tune_batched")
+    return np.array(list(rates))

@@ -172,3 +172,37 @@ def quantize_bf16(x: np.ndarray):
     scale is 1."""
     codes = np.asfortranarray(to_bf16_codes(np.asarray(x, dtype=np.float32)))
     return codes, 1.0
+
+
+E4M3_MAX = 448.0
+
+
+def to_e4m3_codes(x: np.ndarray) -> np.ndarray:
+    """Round finite values to OCP FP8 E4M3 (bias 7, 3 mantissa bits; round to
+    nearest, ties to even; magnitudes above 448 saturate to 448) and return
+    the 8-bit codes."""
+    x = np.asarray(x, dtype=np.float64)
+    sign = (np.signbit(x)).astype(np.uint8) << 7
+    ax = np.minimum(np.abs(x), E4M3_MAX)
+    code = np.zeros(ax.shape, dtype=np.int64)
+    sub = ax < 2.0 ** -6
+    # subnormals (and zero): multiples of 2^-9; q == 8 is the smallest normal
+    code[sub] = np.rint(ax[sub] * 2.0 ** 9).astype(np.int64)
+    nrm = ~sub
+    e = np.floor(np.log2(ax[nrm])).astype(np.int64)
+    q = np.rint(ax[nrm] / np.exp2(e - 3)).astype(np.int64)      # 8 .. 16
+    e = np.where(q == 16, e + 1, e)
+    q = np.where(q == 16, 8, q)
+    code[nrm] = ((e + 7) << 3) | (q - 8)
+    code = np.minimum(code, 0x7E)                                 # saturate at 448
+    return (code.astype(np.uint8) | sign).reshape(x.shape)
+
+
+def quantize_e4m3(x: np.ndarray):
+    """Per-tensor power-of-two absmax scaling to E4M3: returns (codes, s) with
+    x ~= s * decode(codes), s = 2^ceil(log2(absmax / 448))."""
+    x = np.asarray(x, dtype=np.float32)
+    amax = float(np.max(np.abs(x))) if x.size else 0.0
+    s = 1.0 if amax == 0.0 else float(2.0 ** np.ceil(np.log2(amax / E4M3_MAX)))
+    codes = np.asfortranarray(to_e4m3_codes(x.astype(np.float64) / s))
+    return codes, s

@@ -43,8 +43,52 @@ def test_struct_sizes_match_header_layout():
     assert F.FAULT_DTYPE.itemsize == 32
     assert F.FAULT_LOG_DTYPE.itemsize == 64
     assert ctypes.sizeof(F.Config) == 16
-    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4
+    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 4
+    assert F.PROBLEM_DTYPE.itemsize == 96
+    assert ctypes.sizeof(F.Tuned) == 48
     assert W.SITE_DTYPE == F.FAULT_DTYPE
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """sizeof/offsetof of every ABI struct, as the host C++ compiler lays them
+    out from include/ftgemm.h, against the ctypes / numpy mirrors."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("no host compiler")
+    structs = {
+        "ftgemm_event_t": F.EVENT_DTYPE, "ftgemm_fault_t": F.FAULT_DTYPE,
+        "ftgemm_fault_log_t": F.FAULT_LOG_DTYPE, "ftgemm_problem_t": F.PROBLEM_DTYPE,
+    }
+    ctypes_structs = {"ftgemm_report_t": F.Report, "ftgemm_config_t": F.Config, "ftgemm_tuned_t": F.Tuned}
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "ftgemm.h"', 'int main() {']
+    for name, dt in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fld in dt.names:
+            lines.append(f'printf("{name} {fld} %zu\\n", offsetof({name}, {fld}));')
+    for name, st in ctypes_structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fld, _ in st._fields_:
+            lines.append(f'printf("{name} {fld} %zu\\n", offsetof({name}, {fld}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", "-I/opt/rocm/include",
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, fld, val = line.split()
+        got[(name, fld)] = int(val)
+    for name, dt in structs.items():
+        assert got[(name, "size")] == dt.itemsize, name
+        for fld in dt.names:
+            assert got[(name, fld)] == dt.fields[fld][1], (name, fld)
+    for name, st in ctypes_structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for fld, _ in st._fields_:
+            assert got[(name, fld)] == getattr(st, fld).offset, (name, fld)
 
 
 @pytest.mark.parametrize("args,bad", [
