@@ -427,8 +427,8 @@ def bench_irregular(args):
 
 
 KERNEL_SOURCES = {
-    "f32": ("ftgemm_fp32.hip", "ftgemm_abft.hpp", "ftgemm_internal.h"),
-    "bf16": ("ftgemm_bf16.hip", "ftgemm_abft.hpp", "ftgemm_internal.h"),
+    "f32": ("ftgemm_fp32.hip", "ftgemm_fp32.hpp", "ftgemm_abft.hpp", "ftgemm_internal.h"),
+    "bf16": ("ftgemm_bf16.hip", "ftgemm_bf16.hpp", "ftgemm_abft.hpp", "ftgemm_internal.h"),
 }
 
 

@@ -202,8 +202,10 @@ int ftgemm_batched_config(ftgemm_t handle, int p, ftgemm_config_t* config);
  * compiled tile variant of the handle's dtype, each with the check intervals
  * of 1, 2, 4, ... k-steps up to max_k_between_checks (0 = 256) columns of k,
  * on operands of shape (m, n, k) allocated for the purpose (filled with
- * zeros, freed before return), and keeps the fastest configuration for this
- * shape and ft_level in the handle; later ftgemm_run calls with the same
+ * zeros, freed before return): one warm-up round, then five interleaved
+ * rounds, median per candidate.  The default configuration of ftgemm_run is
+ * kept unless a candidate is at least 2% faster.  The result is kept in the
+ * handle for this shape and ft_level; later ftgemm_run calls with the same
  * shape and level use it unless a configuration is forced.  *best receives
  * it.  Synchronises `stream`. */
 int ftgemm_tune(ftgemm_t handle, int64_t m, int64_t n, int64_t k, int ft_level, int max_k_between_checks,

@@ -350,12 +350,24 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         tauc = base * (float)(kp + th.mI + 1) * nb * sa;
         cf = !(fabsf(cres) <= tauc);
     }
+    // per wave: how many rows / columns are flagged and the smallest flagged
+    // index (owners need not be in index order; the loops run only when
+    // something is flagged)
     const unsigned long long rb = __ballot(rf), cb = __ballot(cf);
+    int fr_w = -1, fc_w = -1;
+    for (unsigned long long m = rb; m; m &= m - 1) {
+        const int r = __builtin_amdgcn_readlane(th.my_row, __ffsll((long long)m) - 1);
+        fr_w = (fr_w < 0 || r < fr_w) ? r : fr_w;
+    }
+    for (unsigned long long m = cb; m; m &= m - 1) {
+        const int c = __builtin_amdgcn_readlane(th.my_col, __ffsll((long long)m) - 1);
+        fc_w = (fc_w < 0 || c < fc_w) ? c : fc_w;
+    }
     if (lane == 0) {
         s.census[th.wave][0] = __popcll(rb);
-        s.census[th.wave][1] = rb ? th.wave * 64 + __ffsll((long long)rb) - 1 : -1;
+        s.census[th.wave][1] = fr_w;
         s.census[th.wave][2] = __popcll(cb);
-        s.census[th.wave][3] = cb ? th.wave * 64 + __ffsll((long long)cb) - 1 - G::COL0 : -1;
+        s.census[th.wave][3] = fc_w;
     }
     if constexpr (INJ) {   // complete the fault log entries this check is the first to see
         for (int q = flogged; q < fnext; ++q) {
@@ -374,8 +386,9 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
     for (int w = 0; w < NW; ++w) {
         nr += s.census[w][0];
         ncl += s.census[w][2];
-        if (fr < 0) fr = s.census[w][1];
-        if (fc < 0) fc = s.census[w][3];
+        const int r = s.census[w][1], c = s.census[w][3];
+        if (r >= 0 && (fr < 0 || r < fr)) fr = r;
+        if (c >= 0 && (fc < 0 || c < fc)) fc = c;
     }
     if (nr + ncl == 0) return;
 

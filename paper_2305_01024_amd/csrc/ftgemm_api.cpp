@@ -601,31 +601,63 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
                hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         st = FTGEMM_HIP_ERROR;
     } else {
+        // candidates: every variant with check intervals 1, 2, 4, ... within the cap
+        std::vector<ftgemm_config_t> cand;
         const int nv = variant_count(h->dtype);
-        for (int v = 0; v < nv && st == FTGEMM_OK; ++v) {
+        for (int v = 0; v < nv; ++v) {
             const Variant x = variant_at(h->dtype, v);
             const int64_t nk = (k + x.k_step - 1) / x.k_step;
-            for (int gi = 1; st == FTGEMM_OK; gi *= 2) {
-                if (gi > 1 && ((int64_t)gi * x.k_step > kmax || gi > nk)) break;
-                if (ft_level != 2 && gi > 1) break;   // the interval only matters for online checks
-                h->cfg = {x.m_tile, x.n_tile, x.k_step, gi};
+            for (int gi = 1;; gi *= 2) {
+                if (gi > 1 && ((int64_t)gi * x.k_step > kmax || gi > nk || ft_level != 2)) break;
+                cand.push_back({x.m_tile, x.n_tile, x.k_step, gi});
+            }
+        }
+        ftgemm_config_t dflt;
+        select_variant(h->dtype, m, n, &dflt);
+        if (ft_level == 2)   // the default interval may exceed the cap: clamp it like the candidates
+            while (dflt.check_interval > 1 && (int64_t)dflt.check_interval * dflt.k_step > kmax) dflt.check_interval /= 2;
+        auto once = [&]() {
+            return ftgemm_run(h, m, n, k, 1.0f, A, std::max<int64_t>(1, m), B, std::max<int64_t>(1, k), 0.0f,
+                              static_cast<float*>(C), std::max<int64_t>(1, m), ft_level, 0.f, stream, nullptr);
+        };
+        // interleaved rounds (so drift affects every candidate alike), median per candidate
+        constexpr int kRounds = 5;
+        std::vector<std::vector<float>> t(cand.size());
+        for (int r = -1; r < kRounds && st == FTGEMM_OK; ++r) {
+            for (size_t c = 0; c < cand.size() && st == FTGEMM_OK; ++c) {
+                h->cfg = cand[c];
                 h->forced = true;
-                auto once = [&]() {
-                    return ftgemm_run(h, m, n, k, 1.0f, A, std::max<int64_t>(1, m), B, std::max<int64_t>(1, k), 0.0f,
-                                      static_cast<float*>(C), std::max<int64_t>(1, m), ft_level, 0.f, stream, nullptr);
-                };
-                if (once() != FTGEMM_OK) { st = FTGEMM_HIP_ERROR; break; }   // warm-up
-                const int reps = 3;
-                if (hipEventRecord(e0, stream) != hipSuccess) { st = FTGEMM_HIP_ERROR; break; }
-                for (int r = 0; r < reps; ++r) once();
                 float ms = 0.f;
-                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = FTGEMM_HIP_ERROR; break; }
-                if (pick.m_tile == 0 || ms < pick_ms) {
-                    pick = h->cfg;
-                    pick_ms = ms;
+                if (hipEventRecord(e0, stream) != hipSuccess || once() != FTGEMM_OK ||
+                    hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = FTGEMM_HIP_ERROR;
+                    break;
+                }
+                if (r >= 0) t[c].push_back(ms);   // round -1 warms every candidate up
+            }
+        }
+        if (st == FTGEMM_OK) {
+            auto median = [](std::vector<float> v) {
+                std::sort(v.begin(), v.end());
+                return v[v.size() / 2];
+            };
+            int best = -1;
+            float best_ms = 0.f;
+            for (size_t c = 0; c < cand.size(); ++c)
+                if (std::memcmp(&cand[c], &dflt, sizeof(dflt)) == 0) {
+                    best = (int)c;
+                    best_ms = median(t[c]);
+                }
+            for (size_t c = 0; c < cand.size(); ++c) {
+                const float ms = median(t[c]);
+                if (best < 0 || ms < 0.98f * best_ms) {   // replace the incumbent only on a clear win
+                    best = (int)c;
+                    best_ms = ms;
                 }
             }
+            pick = cand[(size_t)best];
+            pick_ms = best_ms;
         }
     }
     h->forced = was_forced;

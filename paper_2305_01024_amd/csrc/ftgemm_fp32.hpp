@@ -113,18 +113,38 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     // take the all-vector path; this test is uniform across the workgroup.
     // Edge panels load element by element from a clamped address and zero what
     // lies outside the matrix, without divergent branches.
+    // Interior panels are read with buffer loads: the per-lane byte offset of
+    // each slot is fixed for the whole k-loop, the per-step panel origin goes
+    // into the (scalar) resource base and the k-column stride into the scalar
+    // offset, so the loop spends no vector instructions on addresses.  Used
+    // while every offset of a panel fits in 31 bits.
+    const bool bufA = alignA && (int64_t)BK * a.lda * 4 < (int64_t(1) << 31);
+    const bool bufB = alignB && (int64_t)BN * a.ldb * 4 < (int64_t(1) << 31);
+    int voffA[NA], voffB[NB];
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+        const int f = tid + NT * r;
+        voffA[r] = ((f / AIQ) * 4 * (int)a.lda + 4 * (f % AIQ)) * 4;
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int f = tid + NT * r;
+        voffB[r] = ((f / BKQ) * (int)a.ldb + 4 * (f % BKQ)) * 4;
+    }
+    constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
+
     auto load_A = [&](int t) {
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
-        if (alignA && fullk && mI == BM) {
+        if (bufA && fullk && mI == BM) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(Abase + (size_t)k0 * a.lda), (short)0, 0x7fffffff, kRsrcWord3);
 #pragma unroll
-            for (int r = 0; r < NA; ++r) {
-                const int f = tid + NT * r;
-                const int iq = f % AIQ, kq = f / AIQ;
+            for (int r = 0; r < NA; ++r)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    ra[r][e] = *reinterpret_cast<const f32x4*>(Abase + (size_t)(k0 + 4 * kq + e) * a.lda + 4 * iq);
-            }
+                    ra[r][e] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                             rs, voffA[r], e * (int)a.lda * 4, 0));
         } else {
 #pragma unroll
             for (int r = 0; r < NA; ++r) {
@@ -147,13 +167,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     auto load_B = [&](int t) {
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
-        if (alignB && fullk && nJ == BN) {
+        if (bufB && fullk && nJ == BN) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bbase + k0), (short)0, 0x7fffffff,
+                                                              kRsrcWord3);
 #pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
-                const int kq = f % BKQ, jj = f / BKQ;
-                rb[r] = *reinterpret_cast<const f32x4*>(Bbase + (size_t)jj * a.ldb + k0 + 4 * kq);
-            }
+            for (int r = 0; r < NB; ++r)
+                rb[r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB[r], 0, 0));
         } else {
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
@@ -181,10 +200,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
             const int f = tid + NT * r;
             const int iq = f % AIQ, kq = f / AIQ;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {   // row 4 iq + q gets its 4 k as one 16-byte store
-                const f32x4 row = {ra[r][0][q], ra[r][1][q], ra[r][2][q], ra[r][3][q]};
+            for (int q = 0; q < 4; ++q) {   // row 4 iq + q gets its 4 k (element stores: no register shuffles)
                 const int i = 4 * iq + q;
-                *reinterpret_cast<f32x4*>(&op.As[buf][i][4 * (kq ^ aswz(i))]) = row;
+                float* dst = &op.As[buf][i][4 * (kq ^ aswz(i))];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dst[e] = ra[r][e][q];
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e) ws[4 * r + e] = (ra[r][e][0] + ra[r][e][1]) + (ra[r][e][2] + ra[r][e][3]);
