@@ -590,7 +590,6 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int st = FTGEMM_OK;
     ftgemm_config_t pick{};
-    float pick_ms = 0.f;
     const bool was_forced = h->forced;
     const ftgemm_config_t was_cfg = h->cfg;
     if (hipMalloc(&A, esz * (size_t)m * (size_t)k) != hipSuccess || hipMalloc(&B, esz * (size_t)k * (size_t)n) != hipSuccess ||
@@ -657,7 +656,6 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
                 }
             }
             pick = cand[(size_t)best];
-            pick_ms = best_ms;
         }
     }
     h->forced = was_forced;

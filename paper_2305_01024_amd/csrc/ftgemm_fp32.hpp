@@ -136,6 +136,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     auto load_A = [&](int t) {
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
+        int k0e = k0;   // edge-path k origin, opaque to the loop optimiser (no per-step pointer updates)
+        asm volatile("" : "+s"(k0e));
         if (bufA && fullk && mI == BM) {
             const auto rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(Abase + (size_t)k0 * a.lda), (short)0, 0x7fffffff, kRsrcWord3);
@@ -152,7 +154,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
                 const int iq = f % AIQ, kq = f / AIQ;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int gk = k0 + 4 * kq + e, gi = 4 * iq;
+                    const int gk = k0e + 4 * kq + e, gi = 4 * iq;
                     const float* p = Abase + (size_t)gk * a.lda + gi;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -167,6 +169,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     auto load_B = [&](int t) {
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
+        int k0e = k0;   // edge-path k origin, opaque to the loop optimiser (no per-step pointer updates)
+        asm volatile("" : "+s"(k0e));
         if (bufB && fullk && nJ == BN) {
             const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bbase + k0), (short)0, 0x7fffffff,
                                                               kRsrcWord3);
@@ -178,7 +182,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
             for (int r = 0; r < NB; ++r) {
                 const int f = tid + NT * r;
                 const int kq = f % BKQ, jj = f / BKQ;
-                const int gk = k0 + 4 * kq;
+                const int gk = k0e + 4 * kq;
                 const float* p = Bbase + (size_t)jj * a.ldb + gk;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -391,11 +395,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
         }
     };
 
-    auto post = [&](int t) -> bool {   // injection hook and check after k-step t
+    // injection hook and online check after k-step t (the detect-only level
+    // checks once, after the last step, so its loop carries no check)
+    auto post = [&](int t) -> bool {
         if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
         bool do_check = false;
         if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
-        if constexpr (FT == 1) do_check = (t == nk - 1);
         if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
         return do_check;
     };
@@ -412,7 +417,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
         if (!post(t)) __syncthreads();
     }
     step(nk - 1, std::false_type{});
-    post(nk - 1);
+    if constexpr (FT == 1) {
+        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, nk - 1, fnext);
+        check<G, FT, INJ>(acc, sm.ck, a, th, nk - 1, a.K, Rr, na2, Sc, nb2, fnext, flogged);
+    } else {
+        post(nk - 1);
+    }
     epilogue<G>(acc, a, th, 1.0f);
 }
 

@@ -100,17 +100,38 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     const unsigned char* Abase = A + th.i0;
     const unsigned char* Bbase = B + (size_t)th.j0 * a.ldb;
 
+    // Interior panels: buffer loads with per-lane byte offsets fixed for the
+    // whole k-loop and the per-step origin in the scalar resource base (no
+    // vector address arithmetic in the loop), while the offsets fit in 31 bits.
+    const bool bufA = alignA && (int64_t)BK * a.lda < (int64_t(1) << 31);
+    const bool bufB = alignB && (int64_t)BN * a.ldb < (int64_t(1) << 31);
+    const int voffA = 4 * akq * (int)a.lda + 8 * ac;
+    int voffB[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int f = tid + NT * r;
+        voffB[r] = (f / BKC) * (int)a.ldb + 16 * (f % BKC);
+    }
+    constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
+
     auto load_panels = [&](int t) {
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
-        if (alignA && fullk && mI == BM) {
+        // the edge paths take their k origin through an empty asm so that the
+        // loop optimiser cannot turn their per-element pointers into
+        // induction variables advanced on every step of the interior path
+        int k0e = k0;
+        asm volatile("" : "+s"(k0e));
+        if (bufA && fullk && mI == BM) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<unsigned char*>(Abase + (size_t)k0 * a.lda), (short)0, 0x7fffffff, kRsrcWord3);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                ra[e] = *reinterpret_cast<const u32x2*>(Abase + (size_t)(k0 + 4 * akq + e) * a.lda + 8 * ac);
+                ra[e] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voffA, e * (int)a.lda, 0));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gk = k0 + 4 * akq + e, gi = 8 * ac;
+                const int gk = k0e + 4 * akq + e, gi = 8 * ac;
                 const unsigned char* p = Abase + (size_t)gk * a.lda + gi;
                 unsigned v[8];
 #pragma unroll
@@ -123,19 +144,18 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
                 ra[e][1] = v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24);
             }
         }
-        if (alignB && fullk && nJ == BN) {
+        if (bufB && fullk && nJ == BN) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(Bbase + k0), (short)0,
+                                                              0x7fffffff, kRsrcWord3);
 #pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
-                const int kc = f % BKC, jj = f / BKC;
-                rb[r] = *reinterpret_cast<const u32x4*>(Bbase + (size_t)jj * a.ldb + k0 + 16 * kc);
-            }
+            for (int r = 0; r < NB; ++r)
+                rb[r] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB[r], 0, 0));
         } else {
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
                 const int f = tid + NT * r;
                 const int kc = f % BKC, jj = f / BKC;
-                const int gk = k0 + 16 * kc;
+                const int gk = k0e + 16 * kc;
                 const unsigned char* p = Bbase + (size_t)jj * a.ldb + gk;
                 unsigned v[16];
 #pragma unroll
@@ -277,11 +297,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         }
     };
 
+    // injection hook and online check after k-step t (the detect-only level
+    // checks once, after the last step, so its loop carries no check)
     auto post = [&](int t) -> bool {
         if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
         bool do_check = false;
         if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
-        if constexpr (FT == 1) do_check = (t == nk - 1);
         if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
         return do_check;
     };
@@ -294,7 +315,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         if (!post(t)) __syncthreads();
     }
     step(nk - 1, std::false_type{});
-    post(nk - 1);
+    if constexpr (FT == 1) {
+        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, nk - 1, fnext);
+        check<G, FT, INJ>(acc, sm.ck, a, th, nk - 1, a.K, Rr, na2, Sc, nb2, fnext, flogged);
+    } else {
+        post(nk - 1);
+    }
     epilogue<G>(acc, a, th, a.scale);
 }
 
