@@ -50,6 +50,22 @@ struct SmemBF16 {
 __device__ __forceinline__ float bf_lo(unsigned x) { return __uint_as_float(x << 16); }
 __device__ __forceinline__ float bf_hi(unsigned x) { return __uint_as_float(x & 0xffff0000u); }
 
+// x.lo * y.lo + x.hi * y.hi + acc with exact bf16 products (v_dot2_f32_bf16)
+__device__ __forceinline__ float dot2(unsigned x, unsigned y, float acc) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, x), __builtin_bit_cast(bf16x2, y), acc, false);
+}
+// bf16 pairs (1, 1), (1, 0) and (0, 1) as dot2 selectors.  They reach the
+// instruction through scalar registers: the compiler would otherwise fold
+// (1, 0) into the inline constant 1.0, which the packed-bf16 operand does not
+// read as (1, 0).
+constexpr unsigned kBfOnes = 0x3f803f80u;
+constexpr unsigned kBfLo = 0x00003f80u;     // the low half alone
+constexpr unsigned kBfHi = 0x3f800000u;     // the high half alone
+__device__ __forceinline__ unsigned opaque_sgpr(unsigned x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 // One BM x BN output tile (tm, tn) of the problem in `a`, computed by one
 // workgroup of 64 * WM * WN threads with `sm` as its LDS.
 template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
@@ -186,6 +202,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][8 * kc]) = rb[r];
         }
         if constexpr (FT > 0) {
+            // one v_dot2 per packed pair (an FP32 add of an exact product)
+            const unsigned sel_ones = opaque_sgpr(kBfOnes), sel_lo = opaque_sgpr(kBfLo), sel_hi = opaque_sgpr(kBfHi);
             // e^T A for the thread's 4 k over its 8 rows, then over the 32
             // threads of the same k-quad: lane bits 4, 5 in-wave (reduce-
             // scatter leaves k = 4 akq + ((lane >> 4) & 3)), waves in LDS.
@@ -194,7 +212,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             for (int e = 0; e < 4; ++e) {
                 float x = 0.f;
 #pragma unroll
-                for (int d = 0; d < 4; ++d) x += bf_lo(ra[e][d]) + bf_hi(ra[e][d]);
+                for (int d = 0; d < 4; ++d) x = dot2(ra[e][d], sel_ones, x);
                 ws[e] = x;
             }
             ReduceScatter<4, 5, 4>::run(ws, lane);
@@ -209,8 +227,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             for (int r = 0; r < NB; ++r)
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    vs[2 * d] += bf_lo(rb[r][d]);
-                    vs[2 * d + 1] += bf_hi(rb[r][d]);
+                    vs[2 * d] = dot2(rb[r][d], sel_lo, vs[2 * d]);
+                    vs[2 * d + 1] = dot2(rb[r][d], sel_hi, vs[2 * d + 1]);
                 }
             ReduceScatter<8, 5, 3>::run(vs, lane);
             atomicAdd(&op.vsum[slot][8 * (tid % BKC) + ((lane >> 3) & 7)], vs[0]);
@@ -272,9 +290,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
                 const float yhi = d < 2 ? y0[2 * d + 1] : y1[2 * d - 3];
                 ck0 = fmaf(lo, ylo, ck0);
                 ck0 = fmaf(hi, yhi, ck0);
-                // both squares of the packed pair in one v_dot2c_f32_bf16 (bf16 products are exact)
-                const bf16x2 pr = __builtin_bit_cast(bf16x2, xv[d]);
-                nq0 = __builtin_amdgcn_fdot2_f32_bf16(pr, pr, nq0, false);
+                // both squares of the packed pair in one v_dot2 (bf16 products are exact)
+                nq0 = dot2(xv[d], xv[d], nq0);
             }
         }
     };
