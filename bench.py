@@ -191,6 +191,35 @@ def main():
     tf_ft = flop / (ms_ft * 1e-3) / 1e12 if ms_ft else None
     tf_plain = flop / (ms_plain * 1e-3) / 1e12 if ms_plain else None
 
+    # the other levels on the same inputs: detect-only (one check per tile at
+    # the end, the offline scheme), and both levels with recompute of tainted
+    # tiles (clean: the extra launch finds an empty queue)
+    levels = None
+    if ms_ft and ms_plain:
+        levels = {}
+        for name, lvl in (("detect_only", F.FT_DETECT), ("detect_only_recompute", F.FT_DETECT | F.FT_RECOMPUTE),
+                          ("online_recompute", F.FT_CORRECT | F.FT_RECOMPUTE)):
+            t = timed(lambda: call(lvl), args.steps, args.warmup, stream)
+            levels[name] = {"ms": round(t, 4), "overhead_pct": round(100.0 * (t / ms_plain - 1.0), 3)}
+        # recovery: 8 tiles with two faults in one check interval (uncorrectable
+        # online), recomputed by the second launch
+        sites = np.zeros(8, dtype=F.FAULT_DTYPE)
+        for q in range(8):
+            sites[q] = (q, q, 1, 3, 5, W.KIND_ADD, 1e3, 0)
+        two = np.sort(np.concatenate([sites, sites]), order=["tile_m", "tile_n", "kstep"])
+        two["kstep"][1::2] = 2
+        two["row"][1::2] = 40
+        two["col"][1::2] = 50
+        F.ftgemm_set_injection(h, two)
+        t = timed(lambda: call(F.FT_CORRECT | F.FT_RECOMPUTE), 3, 1, stream)
+        rep = F.ReportBuffer(64)
+        st = call(F.FT_CORRECT | F.FT_RECOMPUTE, rep)
+        F.ftgemm_set_injection(h, None)
+        levels["online_recompute_8_uncorrectable_tiles"] = {
+            "ms": round(t, 4), "status": int(st), "uncorrectable": int(rep.report.uncorrectable),
+            "recomputed": int(rep.report.recomputed), "recompute_failed": int(rep.report.recompute_failed)}
+        log(f"levels: {levels}")
+
     # fault injection at a rate per second of GEMM time, bit flips in bits 0..30
     injection = None
     if not args.skip_injection and ms_ft and not bf16:
@@ -257,6 +286,7 @@ def main():
                      "traffic_unit": "bytes per launch (HBM fetch + write, calibrated)",
                      "traffic_source": traffic_src,
                      "kernel": kname + (" FT=2" if ms_ft else " FT=0")},
+        "levels": levels,
         "injection": injection,
         "cpu_baseline": cpu,
     }

@@ -32,7 +32,8 @@
  *
  * Return codes: FTGEMM_OK (0); FTGEMM_UNCORRECTABLE (1, success with a
  * warning: at least one tile saw more than one fault in a check interval, C
- * may be wrong there and the events say where); negative values are errors
+ * may be wrong there and the events say where; with FTGEMM_FT_RECOMPUTE:
+ * a recomputed tile flagged again); negative values are errors
  * listed in enum ftgemm_status.  A handle is not thread-safe; use one handle
  * per stream.
  */
@@ -53,8 +54,19 @@ enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2 };
 /* ft_level: 0 = plain GEMM (fault tolerance compiled out of the kernel);
  * 1 = detect only, one check of the accumulated tile at the end of the
  *     k-loop (the offline, detect-only scheme of section 5.5);
- * 2 = online detect + locate + correct, checks every check interval. */
-enum ftgemm_level { FTGEMM_FT_OFF = 0, FTGEMM_FT_DETECT = 1, FTGEMM_FT_CORRECT = 2 };
+ * 2 = online detect + locate + correct, checks every check interval.
+ * FTGEMM_FT_RECOMPUTE may be OR-ed into level 1 or 2 (ftgemm_run only): a
+ * tile that ends possibly wrong (level 1: any flagged check; level 2: an
+ * uncorrectable pattern) does not write C; a second launch on the same
+ * stream recomputes exactly those tiles, with the same level and no fault
+ * injection, and writes them.  This is the recovery the paper leaves to
+ * recomputation when the checksums cannot locate the error (section 4.1).
+ * It adds one small launch per call (it reads a device counter and exits
+ * when nothing is queued) and needs no host synchronisation or memset, so
+ * with report == NULL the pair of launches can be captured into a HIP graph
+ * once the handle's queue is large enough for the shape (the first call of
+ * a larger shape allocates it). */
+enum ftgemm_level { FTGEMM_FT_OFF = 0, FTGEMM_FT_DETECT = 1, FTGEMM_FT_CORRECT = 2, FTGEMM_FT_RECOMPUTE = 0x10 };
 
 enum ftgemm_status {
     FTGEMM_OK = 0,
@@ -122,6 +134,8 @@ typedef struct {
     int32_t bad_arg;          /* 1-based position of an invalid argument, else 0 */
     float tol_used;           /* threshold factor c the call used */
     int32_t bad_problem;      /* ftgemm_batched: index of the invalid problem, else -1 */
+    uint32_t recomputed;      /* FTGEMM_FT_RECOMPUTE: tiles recomputed by the second launch */
+    uint32_t recompute_failed;/* ... of which the recomputation flagged again (C written as computed) */
     int32_t pad_;
 } ftgemm_report_t;
 
@@ -152,7 +166,8 @@ int ftgemm_select_config(int dtype, int64_t m, int64_t n, int64_t k, int ft_leve
 /* Host-only argument check used by ftgemm_run.  Returns FTGEMM_OK or
  * FTGEMM_INVALID with *bad_arg set to the 1-based position of the offending
  * ftgemm_run argument (2 = m, 3 = n, 4 = k, 7 = lda, 9 = ldb, 12 = ldc,
- * 13 = ft_level, 14 = tol). */
+ * 13 = ft_level, 14 = tol).  ft_level is 0, 1 or 2, optionally with
+ * FTGEMM_FT_RECOMPUTE on 1 or 2. */
 int ftgemm_validate(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc,
                     int ft_level, float tol, int32_t* bad_arg);
 

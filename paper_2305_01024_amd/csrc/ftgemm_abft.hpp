@@ -185,6 +185,7 @@ struct CheckLds {
     ftgemm_fault_t fault[kMaxFaultsPerTile];
     int fslot[kMaxFaultsPerTile];
     int nf;
+    int tainted;            // a check left the tile possibly wrong (cleared at tile start)
 };
 
 template <class G>
@@ -278,6 +279,8 @@ __device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const Launch
 // checksum and ||a||^2, Sc/nb2 the column ones (the same variables may alias
 // under SPLIT, where a thread owns only one of them).  Ends with a workgroup
 // barrier after the census (callers use it as the end-of-step barrier).
+// A check that leaves the tile possibly wrong (any flag at the detect-only
+// level, an uncorrectable pattern at the online level) sets s.tainted.
 template <class G, int FT, bool INJ>
 __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
                       float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
@@ -483,12 +486,61 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
                 a.events[e] = E;
             }
         }
+        if (th.tid == 0 && (kind == FTGEMM_EV_DETECTED || kind == FTGEMM_EV_UNCORRECTABLE)) s.tainted = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// recompute of tainted tiles
+// ---------------------------------------------------------------------------
+// Body of a retry launch: workgroup w recomputes queued tiles w, w + grid,
+// ...; `tile_fn(tm, tn)` runs one tile.  The last workgroup to finish clears
+// the queue for the next call, so the pair of launches needs no memset.
+template <class TileFn>
+__device__ __forceinline__ void retry_queue(const LaunchArgs& a, int ntm, TileFn&& tile_fn) {
+    const unsigned count = a.retry[0];
+    for (unsigned q = blockIdx.x; q < count; q += gridDim.x) {
+        const int t = a.retry_tiles[q];
+        tile_fn(t % ntm, t / ntm);
+        __syncthreads();   // the next tile reuses the LDS
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.retry[1], 1u) == gridDim.x - 1) {
+            atomicExch(&a.retry[0], 0u);
+            atomicExch(&a.retry[1], 0u);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // epilogue: C = alpha * scale * P + beta * C (beta == 0: C is not read)
 // ---------------------------------------------------------------------------
+template <class G>
+__device__ __forceinline__ void epilogue(const Acc<G>& acc, const LaunchArgs& a, const Thread& th, float scale);
+
+// End of a tile.  A tainted tile of a launch with recompute on is queued for
+// the retry launch and leaves C untouched (so beta * C is still available);
+// every other tile runs the epilogue.  In the retry launch every tile is
+// written and counted, a tainted one also as failed.
+template <class G, int FT>
+__device__ __forceinline__ void finish_tile(const Acc<G>& acc, const CheckLds<G>& s, const LaunchArgs& a,
+                                            const Thread& th, float scale) {
+    const bool tainted = FT > 0 && s.tainted != 0;   // written before the last check's final barrier
+    if (tainted && a.retry_tiles && !a.retry_pass) {
+        if (th.tid == 0) {
+            const int ntm = (a.M + G::BM - 1) / G::BM;
+            const unsigned q = atomicAdd(&a.retry[0], 1u);
+            a.retry_tiles[q] = th.tm + ntm * th.tn;
+        }
+        return;
+    }
+    if (a.retry_pass && th.tid == 0) {
+        atomicAdd(&a.counters[CNT_RECOMPUTED], 1u);
+        if (tainted) atomicAdd(&a.counters[CNT_RECOMPUTE_FAILED], 1u);
+    }
+    epilogue<G>(acc, a, th, scale);
+}
 template <class G>
 __device__ __forceinline__ void epilogue(const Acc<G>& acc, const LaunchArgs& a, const Thread& th, float scale) {
     const float alpha = a.alpha * scale;

@@ -26,6 +26,10 @@ struct ftgemm_ctx {
     int n_faults = 0, fault_cap = 0;
     ftgemm_fault_log_t* d_flog = nullptr;
     int flog_cap = 0;
+    // recompute queue: d_retry[0] queued tiles, d_retry[1] retry workgroups done
+    uint32_t* d_retry = nullptr;
+    int32_t* d_retry_tiles = nullptr;
+    int retry_cap = 0;
     // configurations picked by ftgemm_tune, per (m, n, k, ft_level)
     std::vector<ftgemm_tuned_t> tuned;
     // batched plan of the last ftgemm_batched call
@@ -66,6 +70,10 @@ struct DeviceGuard {
 };
 
 int default_interval(int k_step) { return std::max(1, 256 / std::max(1, k_step)); }
+
+// ft_level without / with the recompute flag
+int base_level(int ft_level) { return ft_level & ~FTGEMM_FT_RECOMPUTE; }
+bool wants_recompute(int ft_level) { return (ft_level & FTGEMM_FT_RECOMPUTE) != 0; }
 
 int variant_count(int dtype) {
     return dtype == FTGEMM_BF16 ? bf16_variant_count() : dtype == FTGEMM_F8E4M3 ? fp8_variant_count()
@@ -235,7 +243,7 @@ bool same_plan(const ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
 }
 
 // Counters and events of the last launch into the report.
-int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, uint64_t checks) {
+int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, uint64_t checks, bool recompute = false) {
     FT_HIP(hipStreamSynchronize(stream));
     uint32_t cnt[CNT_N];
     FT_HIP(hipMemcpy(cnt, h->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
@@ -244,12 +252,15 @@ int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, uint
     report->corrected = cnt[CNT_CORRECTED];
     report->uncorrectable = cnt[CNT_UNCORRECTABLE];
     report->checksum_only = cnt[CNT_CHECKSUM_ONLY];
+    report->recomputed = cnt[CNT_RECOMPUTED];
+    report->recompute_failed = cnt[CNT_RECOMPUTE_FAILED];
     const uint32_t logged = std::min<uint32_t>(cnt[CNT_EVENTS], (uint32_t)h->event_cap);
     const uint32_t copy = report->events ? std::min<uint32_t>(logged, report->cap_events) : 0;
     if (copy > 0)
         FT_HIP(hipMemcpy(report->events, h->d_events, sizeof(ftgemm_event_t) * copy, hipMemcpyDeviceToHost));
     report->n_events = copy;
     if (cnt[CNT_EVENTS] > copy && report->events) return FTGEMM_LOG_OVERFLOW;
+    if (recompute) return report->recompute_failed > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
     return report->uncorrectable > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
 }
 
@@ -279,7 +290,8 @@ int ftgemm_validate(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, i
     else if (lda < std::max<int64_t>(1, m)) bad = 7;
     else if (ldb < std::max<int64_t>(1, k)) bad = 9;
     else if (ldc < std::max<int64_t>(1, m)) bad = 12;
-    else if (ft_level < 0 || ft_level > 2) bad = 13;
+    else if (base_level(ft_level) < 0 || base_level(ft_level) > 2 ||
+             (wants_recompute(ft_level) && base_level(ft_level) == 0)) bad = 13;
     else if (!(tol == tol) || tol > 1e30f) bad = 14;   // NaN or absurd
     if (bad_arg) *bad_arg = bad;
     return bad ? FTGEMM_INVALID : FTGEMM_OK;
@@ -311,11 +323,13 @@ int ftgemm_create(ftgemm_t* handle, int dtype, int device) {
     h->flog_cap = kFaultLogCap;
     if (hipMalloc(&h->d_events, sizeof(ftgemm_event_t) * kEventCap) != hipSuccess ||
         hipMalloc(&h->d_counters, sizeof(uint32_t) * CNT_N) != hipSuccess ||
-        hipMalloc(&h->d_flog, sizeof(ftgemm_fault_log_t) * kFaultLogCap) != hipSuccess) {
+        hipMalloc(&h->d_flog, sizeof(ftgemm_fault_log_t) * kFaultLogCap) != hipSuccess ||
+        hipMalloc(&h->d_retry, sizeof(uint32_t) * 2) != hipSuccess) {
         ftgemm_destroy(h);
         return FTGEMM_NO_MEMORY;
     }
-    if (hipMemset(h->d_counters, 0, sizeof(uint32_t) * CNT_N) != hipSuccess) {
+    if (hipMemset(h->d_counters, 0, sizeof(uint32_t) * CNT_N) != hipSuccess ||
+        hipMemset(h->d_retry, 0, sizeof(uint32_t) * 2) != hipSuccess) {
         ftgemm_destroy(h);
         return FTGEMM_HIP_ERROR;
     }
@@ -333,6 +347,8 @@ int ftgemm_destroy(ftgemm_t h) {
         if (h->d_flog) (void)hipFree(h->d_flog);
         if (h->d_bprobs) (void)hipFree(h->d_bprobs);
         if (h->d_bitems) (void)hipFree(h->d_bitems);
+        if (h->d_retry) (void)hipFree(h->d_retry);
+        if (h->d_retry_tiles) (void)hipFree(h->d_retry_tiles);
     }
     delete h;
     return FTGEMM_OK;
@@ -406,6 +422,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
         report->bad_arg = 0;
         report->tol_used = 0.f;
         report->bad_problem = -1;
+        report->recomputed = report->recompute_failed = 0;
         std::memset(&report->config, 0, sizeof(report->config));
     }
     if (!h) {
@@ -435,11 +452,15 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
         return FTGEMM_INVALID;
     }
 
+    const bool recompute = wants_recompute(ft_level);
+    ft_level = base_level(ft_level);
     ftgemm_config_t cfg;
     if (h->forced) cfg = h->cfg;
     else if (!find_tuned(h, m, n, k, ft_level, &cfg)) select_variant(h->dtype, m, n, &cfg);
     const int variant = find_variant(h->dtype, cfg);
     if (variant < 0) return FTGEMM_UNSUPPORTED;
+    const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
+    if (recompute && grow(&h->d_retry_tiles, &h->retry_cap, (int)ntiles) != FTGEMM_OK) return FTGEMM_NO_MEMORY;
 
     const bool inject = h->n_faults > 0;
     if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
@@ -468,17 +489,31 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     a.n_faults = inject ? h->n_faults : 0;
     a.fault_log = h->d_flog;
     a.fault_log_cap = h->flog_cap;
+    a.retry = recompute ? h->d_retry : nullptr;
+    a.retry_tiles = recompute ? h->d_retry_tiles : nullptr;
+    a.retry_pass = 0;
     if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16(variant, inject, a, stream));
     else if (h->dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8(variant, inject, a, stream));
     else FT_HIP(launch_fp32(variant, inject, a, stream));
+    if (recompute) {
+        // the queued tiles again, without injection; one workgroup per compute
+        // unit at most, each walking the queue
+        LaunchArgs r = a;
+        r.retry_pass = 1;
+        r.faults = nullptr;
+        r.n_faults = 0;
+        const int grid = (int)std::min<int64_t>(ntiles, kNumCUs);
+        if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16_retry(variant, r, grid, stream));
+        else if (h->dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8_retry(variant, r, grid, stream));
+        else FT_HIP(launch_fp32_retry(variant, r, grid, stream));
+    }
 
     if (!report) return FTGEMM_OK;
     report->config = cfg;
-    const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
     const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
     const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
                            : ft_level == 1 ? 1 : 0;
-    return fill_report(h, stream, report, (uint64_t)(ntiles * per_tile));
+    return fill_report(h, stream, report, (uint64_t)(ntiles * per_tile), recompute);
 }
 
 int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_level, float tol,
@@ -490,6 +525,7 @@ int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_
         report->bad_arg = 0;
         report->tol_used = 0.f;
         report->bad_problem = -1;
+        report->recomputed = report->recompute_failed = 0;
         std::memset(&report->config, 0, sizeof(report->config));
     }
     int bad = 0;
@@ -583,6 +619,7 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
         max_k_between_checks < 0)
         return FTGEMM_INVALID;
     if (!dtype_supported(h->dtype)) return FTGEMM_UNSUPPORTED;
+    ft_level = base_level(ft_level);   // configurations are kept per level; recompute does not change them
     const int kmax = max_k_between_checks > 0 ? max_k_between_checks : 256;
     const size_t esz = h->dtype == FTGEMM_F32 ? 4 : h->dtype == FTGEMM_BF16 ? 2 : 1;
     DeviceGuard g(h->device);

@@ -71,6 +71,9 @@ __global__ __launch_bounds__(kBatchThreads, 2) void ftgemm_batched_kernel(BatchA
         a.n_faults = b.n_faults;
         a.fault_log = b.fault_log;
         a.fault_log_cap = b.fault_log_cap;
+        a.retry = nullptr;   // no recompute in the batched launch
+        a.retry_tiles = nullptr;
+        a.retry_pass = 0;
         switch (p.variant) {
             case 0: f32::tile<128, 128, 32, 2, 2, FT, INJ>(a, tm, tn, sm.f32_128); break;
             case 1: f32::tile<64, 64, 64, 2, 2, FT, INJ>(a, tm, tn, sm.f32_64); break;

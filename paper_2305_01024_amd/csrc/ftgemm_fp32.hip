@@ -12,6 +12,14 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) 
     f32::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
 }
 
+// Recomputes the tiles a launch of the same variant queued (FT levels only).
+template <int BM, int BN, int BK, int WM, int WN, int FT>
+__global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_retry_kernel(LaunchArgs a) {
+    __shared__ f32::Smem<BM, BN, BK, WM, WN> sm;
+    const int ntm = (a.M + BM - 1) / BM;
+    abft::retry_queue(a, ntm, [&](int tm, int tn) { f32::tile<BM, BN, BK, WM, WN, FT, false>(a, tm, tn, sm); });
+}
+
 __global__ void scale_kernel(float* C, int64_t ldc, int32_t M, int32_t N, float beta) {
     const int64_t total = (int64_t)M * N;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
@@ -57,6 +65,14 @@ hipError_t launch_shape(bool inject, const LaunchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_shape_retry(const LaunchArgs& a, int grid, hipStream_t s) {
+    const dim3 g((unsigned)grid), block(64 * WM * WN);
+    if (a.ft_level == 1) hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 1>), g, block, 0, s, a);
+    else hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 2>), g, block, 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int fp32_variant_count() { return kNumVariants; }
@@ -76,6 +92,17 @@ hipError_t launch_fp32(int idx, bool inject, const LaunchArgs& a, hipStream_t s)
         case 2: return launch_shape<128, 256, 32, 1, 4>(inject, a, s);
         case 3: return launch_shape<128, 128, 32, 2, 2>(inject, a, s);
         case 4: return launch_shape<64, 64, 32, 1, 1>(inject, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t s) {
+    switch (idx) {
+        case 0: return launch_shape_retry<256, 256, 32, 2, 4>(a, grid, s);
+        case 1: return launch_shape_retry<256, 128, 32, 2, 2>(a, grid, s);
+        case 2: return launch_shape_retry<128, 256, 32, 1, 4>(a, grid, s);
+        case 3: return launch_shape_retry<128, 128, 32, 2, 2>(a, grid, s);
+        case 4: return launch_shape_retry<64, 64, 32, 1, 1>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -12,6 +12,22 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_fp8_kernel(LaunchArgs a) 
     fp8::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
 }
 
+// Recomputes the tiles a launch of the same variant queued (FT levels only).
+template <int BM, int BN, int BK, int WM, int WN, int FT>
+__global__ __launch_bounds__(64 * WM * WN) void ftgemm_fp8_retry_kernel(LaunchArgs a) {
+    __shared__ fp8::SmemFP8<BM, BN, BK, WM, WN> sm;
+    const int ntm = (a.M + BM - 1) / BM;
+    abft::retry_queue(a, ntm, [&](int tm, int tn) { fp8::tile<BM, BN, BK, WM, WN, FT, false>(a, tm, tn, sm); });
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_shape_fp8_retry(const LaunchArgs& a, int grid, hipStream_t s) {
+    const dim3 g((unsigned)grid), block(64 * WM * WN);
+    if (a.ft_level == 1) hipLaunchKernelGGL((ftgemm_fp8_retry_kernel<BM, BN, BK, WM, WN, 1>), g, block, 0, s, a);
+    else hipLaunchKernelGGL((ftgemm_fp8_retry_kernel<BM, BN, BK, WM, WN, 2>), g, block, 0, s, a);
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_shape_fp8(bool inject, const LaunchArgs& a, hipStream_t s) {
     const int ntm = (a.M + BM - 1) / BM, ntn = (a.N + BN - 1) / BN;
@@ -50,6 +66,13 @@ int fp8_find_variant(int m_tile, int n_tile, int k_step) {
 hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t s) {
     switch (idx) {
         case 0: return launch_shape_fp8<256, 256, 64, 2, 4>(inject, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fp8_retry(int idx, const LaunchArgs& a, int grid, hipStream_t s) {
+    switch (idx) {
+        case 0: return launch_shape_fp8_retry<256, 256, 64, 2, 4>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -17,6 +17,8 @@ enum Counter : int {
     CNT_UNCORRECTABLE = 3,
     CNT_CHECKSUM_ONLY = 4,
     CNT_FAULTS = 5,        // faults applied by the injection hook
+    CNT_RECOMPUTED = 6,    // tiles recomputed by the retry launch
+    CNT_RECOMPUTE_FAILED = 7,  // retried tiles whose own checks still flagged a fault
     CNT_N = 8
 };
 
@@ -42,6 +44,13 @@ struct LaunchArgs {
     int32_t n_faults;
     ftgemm_fault_log_t* fault_log;   // device applied-fault log
     int32_t fault_log_cap;
+    // Recompute of tainted tiles (nullptr / 0: off).  Main launch: a tainted
+    // tile appends tm + ntm * tn to retry_tiles (retry[0] counts) instead of
+    // writing C.  Retry launch (retry_pass = 1): recomputes the queued tiles;
+    // its last workgroup clears retry[0..1].
+    uint32_t* retry;             // [0] queued tiles, [1] retry workgroups finished
+    int32_t* retry_tiles;        // capacity >= number of tiles of the launch
+    int32_t retry_pass;
 };
 
 struct Variant {
@@ -56,18 +65,22 @@ int fp32_find_variant(int m_tile, int n_tile, int k_step);
 // Launch the FP32 kernel variant `idx` (A, B as float).  `inject` selects the instantiation
 // carrying the fault-injection hook.  Returns a hipError_t.
 hipError_t launch_fp32(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+// Retry launch of variant `idx` over the tiles queued in a.retry_tiles, `grid` workgroups.
+hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 
 // Kernel variants for BF16 operands (A, B as bfloat16 codes).
 int bf16_variant_count();
 Variant bf16_variant(int idx);
 int bf16_find_variant(int m_tile, int n_tile, int k_step);
 hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+hipError_t launch_bf16_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 
 // Kernel variants for FP8 E4M3 operands (A, B as 8-bit codes).
 int fp8_variant_count();
 Variant fp8_variant(int idx);
 int fp8_find_variant(int m_tile, int n_tile, int k_step);
 hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
+hipError_t launch_fp8_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 
 // ---- batched persistent launch ----
 // Device descriptor of one problem of a batched call.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libf
 
 F32, BF16, F8E4M3 = 0, 1, 2
 FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
+FT_RECOMPUTE = 0x10   # OR-ed into FT_DETECT or FT_CORRECT: recompute the tiles that end possibly wrong
 OK, UNCORRECTABLE, INVALID, UNSUPPORTED, HIP_ERROR, NO_MEMORY, LOG_OVERFLOW = 0, 1, -1, -2, -3, -4, -5
 EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED = 1, 2, 3, 4, 5
 FAULT_ADD, FAULT_XOR = 0, 1
@@ -48,7 +49,8 @@ class Report(ctypes.Structure):
                 ("uncorrectable", ctypes.c_uint64), ("checksum_only", ctypes.c_uint64),
                 ("n_events", ctypes.c_uint32), ("cap_events", ctypes.c_uint32),
                 ("events", ctypes.c_void_p), ("config", Config), ("bad_arg", ctypes.c_int32),
-                ("tol_used", ctypes.c_float), ("bad_problem", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("tol_used", ctypes.c_float), ("bad_problem", ctypes.c_int32), ("recomputed", ctypes.c_uint32),
+                ("recompute_failed", ctypes.c_uint32), ("pad_", ctypes.c_int32)]
 
 
 class Tuned(ctypes.Structure):

@@ -43,7 +43,7 @@ def test_struct_sizes_match_header_layout():
     assert F.FAULT_DTYPE.itemsize == 32
     assert F.FAULT_LOG_DTYPE.itemsize == 64
     assert ctypes.sizeof(F.Config) == 16
-    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 4 + 4 + 4
     assert F.PROBLEM_DTYPE.itemsize == 96
     assert ctypes.sizeof(F.Tuned) == 48
     assert W.SITE_DTYPE == F.FAULT_DTYPE
