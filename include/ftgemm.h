@@ -59,8 +59,9 @@ enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2 };
  * tile that ends possibly wrong (level 1: any flagged check; level 2: an
  * uncorrectable pattern) does not write C; a second launch on the same
  * stream recomputes exactly those tiles, with the same level and no fault
- * injection, and writes them.  This is the recovery the paper leaves to
- * recomputation when the checksums cannot locate the error (section 4.1).
+ * injection, and writes them.  Section 5.5 recomputes the whole product
+ * when its offline (detect-only) scheme flags an error; here only the
+ * flagged tiles are recomputed.
  * It adds one small launch per call (it reads a device counter and exits
  * when nothing is queued) and needs no host synchronisation or memset, so
  * with report == NULL the pair of launches can be captured into a HIP graph
