@@ -45,10 +45,11 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--size", type=int, default=8192)
-    p.add_argument("--workload", choices=("square", "batched", "irregular"), default="square",
+    p.add_argument("--workload", choices=("square", "batched", "irregular", "ablation"), default="square",
                    help="square: the headline FP32 8192^3 (default); batched: 1024 uneven FP32/BF16 "
                         "problems in one persistent launch vs a loop of launches; irregular: tall-skinny, "
-                        "small-K and odd shapes, autotuned vs fixed configuration")
+                        "small-K and odd shapes, autotuned vs fixed configuration; ablation: fused online "
+                        "ABFT against the same checks run as separate launches (FP32 8192^3, beta = 0)")
     p.add_argument("--dtype", choices=("f32", "bf16"), default="f32",
                    help="f32: the FP32 square workload (beta = 1); bf16: A, B heavy-tailed N(0,1) "
                         "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel)")
@@ -127,6 +128,8 @@ def main():
         return bench_batched(args)
     if args.workload == "irregular":
         return bench_irregular(args)
+    if args.workload == "ablation":
+        return bench_ablation(args)
     N = args.size
     m = n = k = N
     bf16 = args.dtype == "bf16"
@@ -454,6 +457,76 @@ def bench_irregular(args):
           {"workload": "FP32 irregular FT-GEMM shapes (65536,256,4096), (256,65536,4096), (16384,16384,64), "
                        "(3001,1999,4097), U[-1,1], beta=0, autotuned configuration, one call per shape per step"},
           {"shapes": rows, "roofline": None, "cpu_baseline": None}, args)
+
+
+def bench_ablation(args):
+    """Fused against non-fused ABFT on the same inputs (FP32 N(0,1), alpha = 1,
+    beta = 0, 256 x 256 check tiles, a check every 256 k): the plain kernel,
+    the fused online kernel, and ftgemm_run_nonfused (the same checks as
+    separate launches around the plain kernel on 256-k chunks)."""
+    import torch
+
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    N = args.size
+    m = n = k = N
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2305_01024 + 600)
+    dA = torch.randn(k, m, device="cuda", generator=gen)
+    dB = torch.randn(n, k, device="cuda", generator=gen)
+    dC = torch.zeros(n, m, device="cuda")
+    h = F.ftgemm_create(F.F32, 0)
+    flop = 2.0 * m * n * k
+
+    def fused(level=F.FT_CORRECT, report=None):
+        return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, 0.0, dC.data_ptr(), m, level,
+                            0.0, sh, report)
+
+    def nonfused(report=None):
+        return F.ftgemm_run_nonfused(h, m, n, k, dA.data_ptr(), m, dB.data_ptr(), k, dC.data_ptr(), m, 256,
+                                     stream=sh, report=report)
+
+    for fn in (fused, nonfused):   # clean runs raise no event
+        rep = F.ReportBuffer(16)
+        assert fn(report=rep) == F.OK and rep.report.n_events == 0
+    # the best plain kernel for the non-fused chunk shape (m, n, 256)
+    chunk_cfg = F.ftgemm_tune(h, m, n, 256, F.FT_OFF, 256, sh).as_tuple()
+    log(f"non-fused chunk GEMM configuration {chunk_cfg}; timing plain, fused, non-fused")
+    ms_plain = timed(lambda: fused(F.FT_OFF), args.steps, args.warmup, stream)
+    ms_fused = timed(fused, args.steps, args.warmup, stream)
+    ms_nonfused = timed(nonfused, args.steps, args.warmup, stream)
+    # one additive fault per tile in a seeded chunk: both paths must correct every one
+    g = W.rng(6, W.STREAM_SITES)
+    ntm = ntn = N // 256
+    sites = np.zeros(ntm * ntn, dtype=F.FAULT_DTYPE)
+    for q in range(ntm * ntn):
+        sites[q] = (q // ntn, q % ntn, int(g.integers(0, N // 256)), int(g.integers(0, 256)),
+                    int(g.integers(0, 256)), W.KIND_ADD, 1e4, 0)
+    inj = {}
+    for name, fn, kstep_scale in (("fused", fused, 8), ("nonfused", nonfused, 1)):
+        s2 = sites.copy()
+        s2["kstep"] = s2["kstep"] * kstep_scale   # fused sites are in 32-k steps, non-fused in 256-k chunks
+        F.ftgemm_set_injection(h, s2)
+        rep = F.ReportBuffer(ntm * ntn + 16)
+        st = fn(report=rep)
+        F.ftgemm_set_injection(h, None)
+        inj[name] = {"injected": len(s2), "corrected": int(rep.report.corrected), "status": int(st),
+                     "uncorrectable": int(rep.report.uncorrectable)}
+    F.ftgemm_destroy(h)
+    out = {"plain_ms": round(ms_plain, 4), "fused_ms": round(ms_fused, 4), "nonfused_ms": round(ms_nonfused, 4),
+           "fused_overhead_pct": round(100 * (ms_fused / ms_plain - 1), 2),
+           "nonfused_overhead_pct": round(100 * (ms_nonfused / ms_plain - 1), 2),
+           "fused_speedup_over_nonfused_pct": round(100 * (ms_nonfused / ms_fused - 1), 2),
+           "plain_tflops": round(flop / ms_plain / 1e9, 2), "nonfused_tflops": round(flop / ms_nonfused / 1e9, 2),
+           "nonfused_chunk_config": list(chunk_cfg),
+           "injection_one_per_tile": inj, "roofline": None, "cpu_baseline": None}
+    log(f"ablation: {out}")
+    _line(flop / (ms_fused * 1e-3) / 1e12, ms_fused, "TFLOP/s", "f32",
+          {"workload": f"FP32 {N}^3 N(0,1), alpha=1, beta=0: fused online ABFT vs the same checks as separate "
+                       f"launches around the plain kernel on 256-k chunks"}, out, args)
 
 
 KERNEL_SOURCES = {

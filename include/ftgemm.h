@@ -182,6 +182,24 @@ int ftgemm_run(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
                float* C, int64_t ldc, int ft_level, float tol, hipStream_t stream,
                ftgemm_report_t* report);
 
+/* The same ABFT without the fusion, for measuring what fusing saves
+ * (section 5.4 compares the fused kernels with ABFT applied around a GEMM):
+ * 256 x 256 check tiles, a check every check_k k indices (0 = 256); the
+ * encodings, the reference update per chunk and the check (which reads C
+ * back from memory and locates / corrects / logs exactly as the fused
+ * kernels do) are separate launches around the plain FP32 kernel run on one
+ * k-chunk at a time.  FP32 handles only; alpha must be 1 and beta 0
+ * (FTGEMM_UNSUPPORTED otherwise).  Fault sites of ftgemm_set_injection apply
+ * to C after the GEMM of chunk `kstep` (row/col within the 256 x 256 tile).
+ * Events carry the chunk index as kstep.  The chunk GEMMs use the
+ * configuration ftgemm_tune found for (m, n, check_k) at level 0, if any.
+ * Uses a handle-owned workspace of
+ * (ceil(m/256) + ceil(n/256)) * (k + m + n) + m + n floats, grown on demand. */
+int ftgemm_run_nonfused(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
+                        const void* A, int64_t lda, const void* B, int64_t ldb, float beta,
+                        float* C, int64_t ldc, int check_k, float tol, hipStream_t stream,
+                        ftgemm_report_t* report);
+
 /* One problem of a batched call: C = alpha * (scale_a A) (scale_b B) +
  * beta * C, column-major as in ftgemm_run, with its own dtype (FTGEMM_F32 or
  * FTGEMM_BF16), sizes, scales and device pointers (96 bytes). */

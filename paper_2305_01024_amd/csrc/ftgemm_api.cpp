@@ -30,6 +30,9 @@ struct ftgemm_ctx {
     uint32_t* d_retry = nullptr;
     int32_t* d_retry_tiles = nullptr;
     int retry_cap = 0;
+    // workspace of ftgemm_run_nonfused
+    float* d_nf = nullptr;
+    int64_t nf_cap = 0;
     // configurations picked by ftgemm_tune, per (m, n, k, ft_level)
     std::vector<ftgemm_tuned_t> tuned;
     // batched plan of the last ftgemm_batched call
@@ -349,6 +352,7 @@ int ftgemm_destroy(ftgemm_t h) {
         if (h->d_bitems) (void)hipFree(h->d_bitems);
         if (h->d_retry) (void)hipFree(h->d_retry);
         if (h->d_retry_tiles) (void)hipFree(h->d_retry_tiles);
+        if (h->d_nf) (void)hipFree(h->d_nf);
     }
     delete h;
     return FTGEMM_OK;
@@ -514,6 +518,124 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
                            : ft_level == 1 ? 1 : 0;
     return fill_report(h, stream, report, (uint64_t)(ntiles * per_tile), recompute);
+}
+
+int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
+                        const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int check_k, float tol,
+                        hipStream_t stream, ftgemm_report_t* report) {
+    int32_t bad = 0;
+    if (report) {
+        report->checks = report->detected = report->corrected = 0;
+        report->uncorrectable = report->checksum_only = 0;
+        report->n_events = 0;
+        report->bad_arg = 0;
+        report->tol_used = 0.f;
+        report->bad_problem = -1;
+        report->recomputed = report->recompute_failed = 0;
+        std::memset(&report->config, 0, sizeof(report->config));
+    }
+    if (!h) bad = 1;
+    else if (ftgemm_validate(m, n, k, lda, ldb, ldc, FTGEMM_FT_CORRECT, tol, &bad) != FTGEMM_OK) {}
+    else if (check_k < 0) bad = 13;
+    if (bad) {
+        if (report) report->bad_arg = bad;
+        return FTGEMM_INVALID;
+    }
+    if (h->dtype != FTGEMM_F32 || alpha != 1.0f || beta != 0.0f) return FTGEMM_UNSUPPORTED;
+    const float c = tol > 0.f ? tol : 2.0f;
+    if (report) report->tol_used = c;
+    if (m == 0 || n == 0) return FTGEMM_OK;
+    if (!C) {
+        if (report) report->bad_arg = 11;
+        return FTGEMM_INVALID;
+    }
+    DeviceGuard g(h->device);
+    if (k == 0) {
+        FT_HIP(launch_scale(C, ldc, (int32_t)m, (int32_t)n, 0.0f, stream));
+        if (report) FT_HIP(hipStreamSynchronize(stream));
+        return FTGEMM_OK;
+    }
+    if (!A || !B) {
+        if (report) report->bad_arg = !A ? 6 : 8;
+        return FTGEMM_INVALID;
+    }
+    const int64_t T = kNonFusedTile;
+    const int64_t ntm = (m + T - 1) / T, ntn = (n + T - 1) / T;
+    const int64_t ck = check_k > 0 ? check_k : 256;
+    const int64_t nchunks = (k + ck - 1) / ck;
+    // workspace: W [ntm][k], V [ntn][k], R [ntn][m], S [ntm][n], na2 [m], nb2 [n]
+    const int64_t need = ntm * k + ntn * k + ntn * m + ntm * n + m + n;
+    if (need > h->nf_cap) {
+        if (h->d_nf) (void)hipFree(h->d_nf);
+        h->d_nf = nullptr;
+        h->nf_cap = 0;
+        if (hipMalloc(&h->d_nf, sizeof(float) * (size_t)need) != hipSuccess) return FTGEMM_NO_MEMORY;
+        h->nf_cap = need;
+    }
+    NonFusedArgs nf{};
+    nf.A = static_cast<const float*>(A);
+    nf.B = static_cast<const float*>(B);
+    nf.C = C;
+    nf.lda = lda;
+    nf.ldb = ldb;
+    nf.ldc = ldc;
+    nf.M = (int32_t)m;
+    nf.N = (int32_t)n;
+    nf.K = (int32_t)k;
+    nf.tol_c = c;
+    nf.W = h->d_nf;
+    nf.V = nf.W + ntm * k;
+    nf.R = nf.V + ntn * k;
+    nf.S = nf.R + ntn * m;
+    nf.na2 = nf.S + ntm * n;
+    nf.nb2 = nf.na2 + m;
+    nf.events = h->d_events;
+    nf.event_cap = h->event_cap;
+    nf.counters = h->d_counters;
+    const bool inject = h->n_faults > 0;
+    nf.faults = inject ? h->d_faults : nullptr;
+    nf.n_faults = inject ? h->n_faults : 0;
+    nf.fault_log = h->d_flog;
+    nf.fault_log_cap = h->flog_cap;
+    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
+    FT_HIP(hipMemsetAsync(nf.R, 0, sizeof(float) * (size_t)(ntn * m + ntm * n + m + n), stream));
+    FT_HIP(launch_nonfused_encode(nf, stream));
+
+    // the plain kernel for the chunk shape: a configuration tuned for (m, n, chunk) at
+    // level 0 if the handle has one, else the default
+    ftgemm_config_t cfg;
+    if (!find_tuned(h, m, n, std::min<int64_t>(ck, k), FTGEMM_FT_OFF, &cfg)) select_variant(FTGEMM_F32, m, n, &cfg);
+    const int variant = find_variant(FTGEMM_F32, cfg);
+    if (variant < 0) return FTGEMM_UNSUPPORTED;
+    LaunchArgs a{};
+    a.C = C;
+    a.lda = lda;
+    a.ldb = ldb;
+    a.ldc = ldc;
+    a.M = (int32_t)m;
+    a.N = (int32_t)n;
+    a.alpha = 1.0f;
+    a.scale = 1.0f;
+    a.tol_c = c;
+    a.check_interval = 1;
+    a.ft_level = 0;
+    a.events = h->d_events;
+    a.counters = h->d_counters;
+    a.event_cap = h->event_cap;
+    a.fault_log = h->d_flog;
+    a.fault_log_cap = h->flog_cap;
+    for (int64_t q = 0; q < nchunks; ++q) {
+        const int64_t k0 = q * ck, k1 = std::min(k, k0 + ck);
+        a.A = static_cast<const float*>(A) + k0 * lda;
+        a.B = static_cast<const float*>(B) + k0;
+        a.K = (int32_t)(k1 - k0);
+        a.beta = q == 0 ? 0.0f : 1.0f;
+        FT_HIP(launch_fp32(variant, false, a, stream));
+        FT_HIP(launch_nonfused_chunk(nf, (int)q, (int)k0, (int)k1, stream));
+    }
+    if (!report) return FTGEMM_OK;
+    report->config = ftgemm_config_t{(int32_t)T, (int32_t)T, (int32_t)ck, 1};
+    return fill_report(h, stream, report, (uint64_t)(ntm * ntn * nchunks));
 }
 
 int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_level, float tol,

@@ -126,6 +126,33 @@ int batch_variant_dtype(int v);
 int batch_resident_blocks(int device);
 hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, hipStream_t stream);
 
+// ---- non-fused ABFT (the same checks around the plain kernel, one launch per step) ----
+constexpr int kNonFusedTile = 256;   // check tile, rows and columns
+struct NonFusedArgs {
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    float tol_c;
+    float* W;      // [ntm][K]  e^T A per row tile
+    float* V;      // [ntn][K]  B e per column tile
+    float* R;      // [ntn][M]  row references
+    float* S;      // [ntm][N]  column references
+    float* na2;    // [M]       prefix ||a_i||^2
+    float* nb2;    // [N]       prefix ||b_j||^2
+    ftgemm_event_t* events;
+    int32_t event_cap;
+    uint32_t* counters;
+    const ftgemm_fault_t* faults;    // kstep = chunk index; applied to C after that chunk's GEMM
+    int32_t n_faults;
+    ftgemm_fault_log_t* fault_log;
+    int32_t fault_log_cap;
+};
+hipError_t launch_nonfused_encode(const NonFusedArgs& n, hipStream_t stream);
+// reference update, fault hook and check after chunk c = k indices [k0, k1)
+hipError_t launch_nonfused_chunk(const NonFusedArgs& n, int c, int k0, int k1, hipStream_t stream);
+
 // C = beta * C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t stream);
 

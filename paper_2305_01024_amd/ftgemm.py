@@ -100,6 +100,8 @@ def lib():
         L.ftgemm_validate.argtypes = [i64, i64, i64, i64, i64, i64, i32, f32, ctypes.POINTER(ctypes.c_int32)]
         L.ftgemm_run.argtypes = [vp, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
                                  ctypes.POINTER(Report)]
+        L.ftgemm_run_nonfused.argtypes = [vp, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
+                                          ctypes.POINTER(Report)]
         L.ftgemm_set_injection.argtypes = [vp, vp, i32]
         L.ftgemm_get_injection_log.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
         L.ftgemm_batched.argtypes = [vp, i32, vp, i32, f32, vp, ctypes.POINTER(Report)]
@@ -113,7 +115,7 @@ def lib():
         for name in ("ftgemm_create", "ftgemm_destroy", "ftgemm_set_scales", "ftgemm_set_config",
                      "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
                      "ftgemm_get_injection_log", "ftgemm_batched", "ftgemm_batched_config", "ftgemm_tune", "ftgemm_get_tuned",
-                     "ftgemm_add_tuned", "ftgemm_tune_batched"):
+                     "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -179,6 +181,17 @@ def ftgemm_run(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: i
     st = lib().ftgemm_run(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
                           report.ptr() if report is not None else None)
     return _check(st, "ftgemm_run")
+
+
+def ftgemm_run_nonfused(handle: int, m: int, n: int, k: int, A: int, lda: int, B: int, ldb: int, C: int,
+                        ldc: int, check_k: int = 0, tol: float = 0.0, stream: int = 0,
+                        report: ReportBuffer | None = None, alpha: float = 1.0, beta: float = 0.0) -> int:
+    """The same ABFT as ftgemm_run, not fused (separate launches around the
+    plain FP32 kernel on k-chunks of check_k).  Returns the status (0 or 1);
+    raises FtgemmError on negative statuses."""
+    st = lib().ftgemm_run_nonfused(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, check_k, tol, stream,
+                                   report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_run_nonfused")
 
 
 def ftgemm_set_injection(handle: int, faults: np.ndarray | None) -> None:
