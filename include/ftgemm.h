@@ -183,7 +183,7 @@ int ftgemm_run(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
                ftgemm_report_t* report);
 
 /* The same ABFT without the fusion, for measuring what fusing saves
- * (section 5.4 compares the fused kernels with ABFT applied around a GEMM):
+ * (sections 5.2-5.4 compare the fused kernels with ABFT applied around a GEMM):
  * 256 x 256 check tiles, a check every check_k k indices (0 = 256); the
  * encodings, the reference update per chunk and the check (which reads C
  * back from memory and locates / corrects / logs exactly as the fused

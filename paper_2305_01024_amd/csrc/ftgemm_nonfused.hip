@@ -7,7 +7,7 @@
 //     GEMM      C += A[:, chunk] B[chunk, :]  (the plain FP32 kernel, FT compiled out)
 //     update    R += A[:, chunk] V[chunk], S += W[chunk] B[chunk, :], prefix norms (Eq. 4)
 //     check     row and column sums of C read back from memory against R and S
-// It exists to measure what fusing saves (the comparison of section 5.4):
+// It exists to measure what fusing saves (the comparisons of sections 5.2-5.4):
 // the check reads C from HBM after every chunk and the chunk GEMMs re-read
 // and re-write it, where the fused kernels keep the tile in registers.
 #include <algorithm>
