@@ -396,7 +396,11 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
     if (nr + ncl == 0) return;
 
     // rare path: something was flagged (uniform branch)
-    const bool correct = (FT == 2) && nr == 1 && ncl == 1;
+    // online level: compile-time in the FT = 2 kernels; the FT = 1 (detect-only)
+    // kernels take it from the arguments, so that their code matches the
+    // online kernels' and the compiler schedules their loops alike
+    const bool online = (FT == 2) || a.ft_level == 2;
+    const bool correct = online && nr == 1 && ncl == 1;
     if (th.my_row >= 0 && th.my_row == fr) { s.bc[0] = Rr; s.bc[1] = rres; s.bc[2] = taur; }
     if (th.my_col >= 0 && th.my_col == fc) { s.bc[3] = cres; s.bc[4] = tauc; }
     // Coordinates of (fr, fc) in the accumulator layout; all but the lane
@@ -462,11 +466,11 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         }
     } else {
         int kind;
-        if constexpr (FT == 1) kind = FTGEMM_EV_DETECTED;
+        if (!online) kind = FTGEMM_EV_DETECTED;
         else kind = (nr == 1 && ncl == 0) ? FTGEMM_EV_CHECKSUM_ROW
                   : (nr == 0 && ncl == 1) ? FTGEMM_EV_CHECKSUM_COL
                   : FTGEMM_EV_UNCORRECTABLE;
-        if constexpr (FT == 2) {   // re-base the flagged checksums on the accumulator
+        if (online) {   // re-base the flagged checksums on the accumulator
             if (rf) Rr += rres;
             if (cf) Sc += cres;
         }

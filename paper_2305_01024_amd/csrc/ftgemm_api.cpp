@@ -483,7 +483,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     a.beta = beta;
     a.scale = h->dtype == FTGEMM_F32 ? 1.0f : h->scale_a * h->scale_b;
     a.tol_c = c;
-    a.check_interval = cfg.check_interval;
+    a.check_interval = ft_level == 1 ? INT32_MAX : cfg.check_interval;   // detect-only: after the last step
     a.ft_level = ft_level;
     a.problem = 0;
     a.events = h->d_events;

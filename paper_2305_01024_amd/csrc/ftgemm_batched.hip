@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBatchThreads, 2) void ftgemm_batched_kernel(BatchA
         a.beta = p.beta;
         a.scale = p.scale;
         a.tol_c = b.tol_c;
-        a.check_interval = p.check_interval;
+        a.check_interval = b.ft_level == 1 ? 0x7fffffff : p.check_interval;   // detect-only: after the last step
         a.ft_level = b.ft_level;
         a.problem = item.problem;
         a.events = b.events;

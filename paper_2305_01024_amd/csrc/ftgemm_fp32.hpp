@@ -396,12 +396,13 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
         }
     };
 
-    // injection hook and online check after k-step t (the detect-only level
-    // checks once, after the last step, so its loop carries no check)
+    // injection hook and online check after k-step t.  The detect-only level
+    // has the same loop: the host sets its check interval beyond the last
+    // k-step, so it checks once, after the last step.
     auto post = [&](int t) -> bool {
         if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
         bool do_check = false;
-        if constexpr (FT == 2) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
+        if constexpr (FT > 0) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
         if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
         return do_check;
     };
@@ -418,12 +419,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
         if (!post(t)) __syncthreads();
     }
     step(nk - 1, std::false_type{});
-    if constexpr (FT == 1) {
-        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, nk - 1, fnext);
-        check<G, FT, INJ>(acc, sm.ck, a, th, nk - 1, a.K, Rr, na2, Sc, nb2, fnext, flogged);
-    } else {
-        post(nk - 1);
-    }
+    post(nk - 1);
     finish_tile<G, FT>(acc, sm.ck, a, th, 1.0f);
 }
 
