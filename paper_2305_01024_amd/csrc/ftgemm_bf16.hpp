@@ -257,9 +257,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
     constexpr int XBUF = BM * KP;   // == BN * KP (square tiles)
     static_assert(BM == BN, "owner addressing assumes square tiles");
 
-    // one k16 sub-step: an MFMA on every block of the wave tile
-    auto mfma_sub = [&](int cur, int s) {
-        bf16x8 bx[NI], ay[MI];
+    // operand fragments of sub-step s (16 k) of buffer `cur`
+    auto load_frags = [&](int cur, int s, bf16x8* bx, bf16x8* ay) {
 #pragma unroll
         for (int bj = 0; bj < NI; ++bj)
             bx[bj] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
@@ -268,6 +267,25 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
         for (int bi = 0; bi < MI; ++bi)
             ay[bi] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
                                                     &op.As[cur][wm * TM + 32 * bi + l32][16 * s + 8 * hh]));
+    };
+    // The plain kernel reads the fragments of sub-step s + 1 before issuing
+    // the MFMAs of sub-step s (within a k-step); the FT kernels have no
+    // registers to spare for the second set.
+    bf16x8 bxq[2][NI], ayq[2][MI];
+
+    // one k16 sub-step: an MFMA on every block of the wave tile
+    auto mfma_sub = [&](int cur, int s) {
+        bf16x8 bxl[NI], ayl[MI];
+        bf16x8* bx = bxl;
+        bf16x8* ay = ayl;
+        if constexpr (FT == 0) {
+            if (s == 0) load_frags(cur, 0, bxq[0], ayq[0]);
+            if (s + 1 < BK / 16) load_frags(cur, s + 1, bxq[(s + 1) & 1], ayq[(s + 1) & 1]);
+            bx = bxq[s & 1];
+            ay = ayq[s & 1];
+        } else {
+            load_frags(cur, s, bxl, ayl);
+        }
 #pragma unroll
         for (int bi = 0; bi < MI; ++bi)
 #pragma unroll

@@ -92,6 +92,21 @@ def test_clean_matches_oracle(h, shape):
     assert err <= TOL_ACC[h[1][4]], err
 
 
+@pytest.mark.parametrize("shape", [(512, 768, 640), (300, 520, 200), (1000, 37, 999)])
+def test_plain_level_matches_oracle(h, shape):
+    """ft_level 0 (the plain kernel, FT compiled out): same bar on the product,
+    no event, including ragged tiles and a partial last k-step."""
+    m, n, k = shape
+    Ac, sa = _quant(h[1], W.normal((m, k), 301, 0))
+    Bc, sb = _quant(h[1], W.normal((k, n), 301, 1))
+    A, B = _decoded(h, Ac, Bc)
+    C0 = W.normal((m, n), 301, 2)
+    st, C, rep = _run(h, Ac, Bc, sa, sb, C0=C0, alpha=0.5, beta=2.0, level=F.FT_OFF)
+    ref = O.gemm(A, B, C0, alpha=0.5 * sa * sb, beta=2.0)
+    assert st == F.OK and rep.report.n_events == 0 and rep.report.checks == 0
+    assert rel_fro(C, ref) <= TOL_ACC[h[1][4]]
+
+
 def test_integer_operands_exact(h):
     Ac, sa = _quant(h[1], W.integers((320, 448), 301, 0))
     Bc, sb = _quant(h[1], W.integers((448, 288), 301, 1))

@@ -183,3 +183,40 @@ def test_recompute_flag_validation(h):
     with pytest.raises(F.FtgemmError):
         F.ftgemm_batched(h, F.make_problems(0), ft_level=F.FT_CORRECT | F.FT_RECOMPUTE, report=rep)
     assert rep.report.bad_arg == 4
+
+
+def test_recompute_pair_captured_in_a_graph(h):
+    """With recompute on and no report, ftgemm_run issues two launches and
+    no memset: after one eager call of the shape (which sizes the queue) the
+    pair can be captured into a HIP graph.  Each of several replays, with
+    eager work between them, reproduces the eager result bit for bit, and a
+    later eager call finds the queue empty."""
+    import torch
+    from gpu_util import dev, host
+    m = n = k = 512
+    A = W.uniform((m, k), 407, 0)
+    B = W.uniform((k, n), 407, 1)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, m), device="cuda")
+
+    def call():
+        return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, 0.0, dC.data_ptr(), m,
+                            F.FT_CORRECT | F.FT_RECOMPUTE, 0.0, torch.cuda.current_stream().cuda_stream, None)
+    assert call() == F.OK
+    torch.cuda.synchronize()
+    eager = host(dC, m, n).copy()
+    assert rel_fro(eager, O.gemm(A, B)) <= TOL_F32
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call()
+    for rep in range(3):
+        dC.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(dC, m, n), eager), rep
+        x = torch.randn(1024, 1024, device="cuda")
+        (x @ x).sum().item()          # unrelated eager work between replays
+    del graph
+    st, C, rep = run(h, A, B, ft_level=F.FT_CORRECT | F.FT_RECOMPUTE)
+    assert st == F.OK and rep.report.recomputed == 0
