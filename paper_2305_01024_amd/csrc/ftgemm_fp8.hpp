@@ -1,7 +1,7 @@
 // ftgemm_fp8.hpp -- FP8 (OCP E4M3) input online ABFT GEMM kernels for gfx950.
 //
 // C = alpha * (scale_a * A) (scale_b * B) + beta * C with A, B as E4M3 codes
-// and FP32 accumulation on v_mfma_f32_32x32x16_fp8_fp8.  The fault tolerance
+// and FP32 accumulation on v_mfma_scale_f32_32x32x64_f8f6f4 (unit scales).  The fault tolerance
 // is the threadblock-level online ABFT of the FP32 kernels (section 2.2
 // Eq. 1-4, section 4.2.3): every E4M3 value converts exactly to FP32
 // (v_cvt_pk_f32_fp8), so the encodings e^T A and B e, the reference
@@ -10,8 +10,8 @@
 // epilogue, outside the checked region.
 //
 // Layout: both operands sit in LDS k-contiguous ([row][k], 16-byte padded
-// rows): lane l of a 32x32x16 MFMA supplies 8 consecutive k (8 bytes) of one
-// row.  B (column-major K x N) is k-contiguous already; A (column-major
+// rows): lane l of a 32x32x64 MFMA supplies 32 consecutive k (32 bytes) of
+// one row.  B (column-major K x N) is k-contiguous already; A (column-major
 // M x K) is i-contiguous, so each thread loads an 8-row x 4-k byte block
 // (four 8-byte loads) and transposes it in registers on the way to LDS.  As
 // in the other kernels the MFMA computes P^T = B^T A^T, so lane l % 32 owns
@@ -247,20 +247,32 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     const unsigned char* const x_arr = row_role ? &op.As[0][0][0] : &op.Bs[0][0][0];
     constexpr int XBUF = BM * KP;   // == BN * KP
 
-    // one k16 sub-step: an MFMA on every block of the wave tile
+    // The whole 64-k step is one v_mfma_scale_f32_32x32x64_f8f6f4 per block
+    // (E4M3 operands, unit block scales): lane l supplies 32 consecutive k
+    // (32 bytes, two 16-byte LDS reads) of one row, the lane halves taking
+    // k 0..31 and 32..63.  Both operands are read with the same lane -> k
+    // assignment, so every product pairs a_ik with b_kj.  Sub-step s issues
+    // the MFMAs of row block s; the column-block fragments are read at s = 0
+    // and kept for the step.
+    static_assert(MI == BK / 16 && BK == 64, "one row block per sub-step, one MFMA per block per step");
+    typedef int i32x8 __attribute__((ext_vector_type(8)));
+    constexpr int kScaleOne = 127;   // E8M0 block scale 2^0
+    i32x8 bxk[NI];
+    auto frag = [&](const unsigned char* p) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(p);
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(p + 16);
+        return i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+    };
     auto mfma_sub = [&](int cur, int s) {
-        long bx[NI], ay[MI];
+        if (s == 0) {
+#pragma unroll
+            for (int bj = 0; bj < NI; ++bj) bxk[bj] = frag(&op.Bs[cur][wn * TN + 32 * bj + l32][32 * hh]);
+        }
+        const i32x8 ay = frag(&op.As[cur][wm * TM + 32 * s + l32][32 * hh]);
 #pragma unroll
         for (int bj = 0; bj < NI; ++bj)
-            bx[bj] = *reinterpret_cast<const long*>(&op.Bs[cur][wn * TN + 32 * bj + l32][16 * s + 8 * hh]);
-#pragma unroll
-        for (int bi = 0; bi < MI; ++bi)
-            ay[bi] = *reinterpret_cast<const long*>(&op.As[cur][wm * TM + 32 * bi + l32][16 * s + 8 * hh]);
-#pragma unroll
-        for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < NI; ++bj)
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(bx[bj], ay[bi], acc[bi][bj], 0, 0, 0);
+            acc[s][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bxk[bj], ay, acc[s][bj], 0, 0, 0, kScaleOne,
+                                                                        0, kScaleOne);
     };
 
     // reference checksum update (Eq. 4) for the same 16 k
