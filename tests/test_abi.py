@@ -115,6 +115,23 @@ def test_validate_level_and_tol():
     assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, tol=-1.0)[1] == 0   # <= 0 selects the default
 
 
+def test_validate_recompute_flag():
+    """FTGEMM_FT_RECOMPUTE is accepted on the fault-tolerant levels only."""
+    for lvl in (F.FT_DETECT, F.FT_CORRECT):
+        assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=lvl | F.FT_RECOMPUTE) == (F.OK, 0)
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=F.FT_OFF | F.FT_RECOMPUTE)[1] == 13
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=3 | F.FT_RECOMPUTE)[1] == 13
+    assert F.ftgemm_validate(4, 4, 4, 4, 4, 4, ft_level=F.FT_CORRECT | 0x20)[1] == 13
+
+
+def test_nonfused_and_batched_with_null_handle_are_invalid():
+    rep = F.ReportBuffer(4)
+    st = F.lib().ftgemm_run_nonfused(None, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0, 0.0, None, rep.ptr())
+    assert st == F.INVALID and rep.report.bad_arg == 1
+    st = F.lib().ftgemm_batched(None, 0, None, F.FT_CORRECT, 0.0, None, rep.ptr())
+    assert st == F.INVALID and rep.report.bad_arg == 1
+
+
 def test_select_config_fills_the_gpu_and_checks_every_256_k():
     for (m, n) in [(8192, 8192), (4096, 4096), (2048, 2048), (65536, 256), (256, 65536), (3001, 1999),
                    (100, 100)]:
