@@ -463,7 +463,10 @@ def bench_ablation(args):
     """Fused against non-fused ABFT on the same inputs (FP32 N(0,1), alpha = 1,
     beta = 0, 256 x 256 check tiles, a check every 256 k): the plain kernel,
     the fused online kernel, and ftgemm_run_nonfused (the same checks as
-    separate launches around the plain kernel on 256-k chunks)."""
+    separate launches around the plain kernel on 256-k chunks).  Then the
+    check granularity on one compute tile (128 x 128, four wavefronts): plain,
+    threadblock-level checks (128 x 128 check tiles) and warp-level checks
+    (one 64 x 64 check tile per wavefront)."""
     import torch
 
     from paper_2305_01024_amd import ftgemm as F
@@ -515,6 +518,7 @@ def bench_ablation(args):
         F.ftgemm_set_injection(h, None)
         inj[name] = {"injected": len(s2), "corrected": int(rep.report.corrected), "status": int(st),
                      "uncorrectable": int(rep.report.uncorrectable)}
+    gran = bench_granularity(h, m, n, k, fused, args, stream)
     F.ftgemm_destroy(h)
     out = {"plain_ms": round(ms_plain, 4), "fused_ms": round(ms_fused, 4), "nonfused_ms": round(ms_nonfused, 4),
            "fused_overhead_pct": round(100 * (ms_fused / ms_plain - 1), 2),
@@ -522,11 +526,64 @@ def bench_ablation(args):
            "fused_speedup_over_nonfused_pct": round(100 * (ms_nonfused / ms_fused - 1), 2),
            "plain_tflops": round(flop / ms_plain / 1e9, 2), "nonfused_tflops": round(flop / ms_nonfused / 1e9, 2),
            "nonfused_chunk_config": list(chunk_cfg),
-           "injection_one_per_tile": inj, "roofline": None, "cpu_baseline": None}
+           "injection_one_per_tile": inj, "check_granularity": gran, "roofline": None, "cpu_baseline": None}
     log(f"ablation: {out}")
     _line(flop / (ms_fused * 1e-3) / 1e12, ms_fused, "TFLOP/s", "f32",
           {"workload": f"FP32 {N}^3 N(0,1), alpha=1, beta=0: fused online ABFT vs the same checks as separate "
                        f"launches around the plain kernel on 256-k chunks"}, out, args)
+
+
+def bench_granularity(h, m, n, k, fused, args, stream):
+    """Threadblock-level against warp-level checks on the 128 x 128 compute
+    tile (2 x 2 wavefronts): times, and one +1e4 fault in each of the four
+    wavefront tiles of 1024 seeded compute tiles, all four at the same k-step.
+    Warp-level checks correct every fault; threadblock-level checks see four
+    in one check interval of one tile and can only report them."""
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+    tile = (128, 128, 32, 8, 128, 128)
+    wave = (128, 128, 32, 8, 64, 64)
+    ms = {}
+    for name, cfg, level in (("plain", tile, F.FT_OFF), ("threadblock", tile, F.FT_CORRECT),
+                             ("wavefront", wave, F.FT_CORRECT)):
+        F.ftgemm_set_config(h, cfg)
+        ms[name] = timed(lambda: fused(level), args.steps, args.warmup, stream)
+    g = W.rng(7, W.STREAM_SITES)
+    ntm, ntn, nk = m // 128, n // 128, k // 32
+    pick = g.choice(ntm * ntn, size=min(1024, ntm * ntn), replace=False)
+    wsites = np.zeros(4 * len(pick), dtype=F.FAULT_DTYPE)
+    q = 0
+    for t in sorted(int(x) for x in pick):
+        tm, tn, ks = t // ntn, t % ntn, int(g.integers(0, nk))
+        for a in range(2):
+            for b in range(2):
+                wsites[q] = (2 * tm + a, 2 * tn + b, ks, int(g.integers(0, 64)), int(g.integers(0, 64)),
+                             W.KIND_ADD, 1e4, 0)
+                q += 1
+    tsites = wsites.copy()   # the same elements in compute-tile coordinates
+    tsites["tile_m"], tsites["tile_n"] = wsites["tile_m"] // 2, wsites["tile_n"] // 2
+    tsites["row"] = wsites["row"] + 64 * (wsites["tile_m"] % 2)
+    tsites["col"] = wsites["col"] + 64 * (wsites["tile_n"] % 2)
+    wsites = wsites[np.lexsort((wsites["kstep"], wsites["tile_n"], wsites["tile_m"]))]
+    tsites = tsites[np.lexsort((tsites["kstep"], tsites["tile_n"], tsites["tile_m"]))]
+    inj = {}
+    for name, cfg, sites in (("threadblock", tile, tsites), ("wavefront", wave, wsites)):
+        F.ftgemm_set_config(h, cfg)
+        F.ftgemm_set_injection(h, sites)
+        rep = F.ReportBuffer(len(sites) + 16)
+        st = fused(F.FT_CORRECT, rep)
+        F.ftgemm_set_injection(h, None)
+        inj[name] = {"injected": len(sites), "corrected": int(rep.report.corrected),
+                     "uncorrectable": int(rep.report.uncorrectable), "status": int(st)}
+    F.ftgemm_set_config(h, None)
+    flop = 2.0 * m * n * k
+    out = {"compute_tile": [128, 128], "check_every_k": 256,
+           "ms": {x: round(v, 4) for x, v in ms.items()},
+           "tflops": {x: round(flop / v / 1e9, 2) for x, v in ms.items()},
+           "overhead_pct": {x: round(100 * (ms[x] / ms["plain"] - 1), 2) for x in ("threadblock", "wavefront")},
+           "injection_four_per_compute_tile_same_step": inj}
+    log(f"check granularity: {out}")
+    return out
 
 
 KERNEL_SOURCES = {

@@ -89,8 +89,9 @@ enum ftgemm_event_kind {
 
 enum ftgemm_fault_kind { FTGEMM_FAULT_ADD = 0, FTGEMM_FAULT_XOR = 1 };
 
-/* One detection event.  row/col are tile-relative (row index within the m
- * range of the tile, column index within its n range); value_before/after are
+/* One detection event.  (tile_m, tile_n) is the check tile, row/col are
+ * relative to it (row index within the m range of the check tile, column
+ * index within its n range; -1 where nothing was flagged); value_before/after are
  * the accumulator element before and after correction (alpha/beta not yet
  * applied). */
 typedef struct {
@@ -99,7 +100,7 @@ typedef struct {
 } ftgemm_event_t;
 
 /* A fault site for the injection hook: after the accumulator update of k-step
- * `kstep`, element (row, col) of tile (tile_m, tile_n) of problem `problem`
+ * `kstep`, element (row, col) of check tile (tile_m, tile_n) of problem `problem`
  * gets `+= payload` (FTGEMM_FAULT_ADD) or has bit (int)payload flipped
  * (FTGEMM_FAULT_XOR). */
 typedef struct {
@@ -116,10 +117,21 @@ typedef struct {
     float old_v, new_v, r_row, r_col, tau_row, tau_col, pad0_, pad1_;
 } ftgemm_fault_log_t;
 
-/* Kernel configuration: compute tile (= check tile) m_tile x n_tile, k-step
- * k_step, a check every check_interval k-steps (and after the last). */
+/* Kernel configuration: compute tile m_tile x n_tile (one workgroup), k-step
+ * k_step, a check every check_interval k-steps (and after the last), and the
+ * check tile check_m x check_n: the block of C whose row and column sums are
+ * compared with its own reference checksums and in which one fault per check
+ * interval can be corrected.  The check tile is either the compute tile
+ * (threadblock-level ABFT, section 4.2.3; 0 x 0 also selects it) or, for the
+ * FP32 128x128 tile (2 x 2 wavefronts), the 64x64 sub-tile of one wavefront
+ * (warp-level ABFT, section 4.2.2: per-wavefront encodings e^T A_w and B_w e
+ * and reference checksums).  Events and fault sites address
+ * check tiles: tile_m, tile_n count check tiles of C, row and col are
+ * relative to the check tile.  The library reports the check shape it used
+ * (never 0). */
 typedef struct {
     int32_t m_tile, n_tile, k_step, check_interval;
+    int32_t check_m, check_n;
 } ftgemm_config_t;
 
 typedef struct {
@@ -157,7 +169,10 @@ int ftgemm_destroy(ftgemm_t handle);
 int ftgemm_set_scales(ftgemm_t handle, float scale_a, float scale_b);
 
 /* Force a kernel configuration for later calls (NULL: automatic selection).
- * Returns FTGEMM_UNSUPPORTED if no kernel variant has that tile shape. */
+ * Returns FTGEMM_UNSUPPORTED if no kernel variant has that tile and check
+ * shape.  A wavefront check tile applies to ft_level 1 and 2; at level 0
+ * the configuration runs the plain kernel of its compute tile.  Automatic
+ * selection picks compute-tile checks only. */
 int ftgemm_set_config(ftgemm_t handle, const ftgemm_config_t* config);
 
 /* Host-only: the configuration automatic selection picks for a shape. */
@@ -233,7 +248,8 @@ int ftgemm_batched(ftgemm_t handle, int count, const ftgemm_problem_t* probs, in
 int ftgemm_batched_config(ftgemm_t handle, int p, ftgemm_config_t* config);
 
 /* Autotuner, in place of the paper's kernel-template generator: times every
- * compiled tile variant of the handle's dtype, each with the check intervals
+ * compiled tile variant of the handle's dtype (at ft_level 1 and 2 both check
+ * granularities, compute tile and wavefront tile), each with the check intervals
  * of 1, 2, 4, ... k-steps up to max_k_between_checks (0 = 256) columns of k,
  * on operands of shape (m, n, k) allocated for the purpose (filled with
  * zeros, freed before return): one warm-up round, then five interleaved
@@ -267,7 +283,8 @@ int ftgemm_tune_batched(ftgemm_t handle, hipStream_t stream, double* rates);
 /* Fault injection hook (compiled into dedicated kernel instantiations; the
  * production kernels contain no injection code).  `faults` is a host array
  * of n sites, copied to the device; n == 0 disables injection.  Sites must
- * be sorted by (problem, tile_m, tile_n, kstep); at most 32 per tile. */
+ * be sorted by (problem, tile_m, tile_n, kstep); at most 32 per compute tile
+ * (all its check tiles together). */
 int ftgemm_set_injection(ftgemm_t handle, const ftgemm_fault_t* faults, int n);
 
 /* Copy the applied-fault log of the last call into `out` (host array of cap

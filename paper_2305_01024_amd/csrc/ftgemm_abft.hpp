@@ -188,6 +188,18 @@ struct CheckLds {
     int tainted;            // a check left the tile possibly wrong (cleared at tile start)
 };
 
+// Extra LDS of the wavefront-tile check: per wave, the flag census of each
+// check tile it holds owners for, and the checksum values of each check
+// tile's first flagged row and column.
+template <class G>
+struct WaveCheckLds : CheckLds<G> {
+    static constexpr int NR = G::WM > G::WN ? G::WM : G::WN;
+    int wcen[G::NW][NR][2];     // (#flagged, first flagged index) per wave and check tile
+    int wany[G::NW];            // the wave flagged anything
+    float bw[G::NW][5];         // per check tile: R, r_row, tau_row, r_col, tau_col
+    int tdec[G::NW][4];         // per check tile: #rows, #columns flagged, first row, first column
+};
+
 template <class G>
 using Acc = f32x16[G::MI][G::NI];
 
@@ -195,13 +207,24 @@ using Acc = f32x16[G::MI][G::NI];
 // fault injection hook (compiled only into INJ kernels)
 // ---------------------------------------------------------------------------
 // Collect this tile's fault sites into LDS, ordered by (kstep, row, col).
-template <class G>
+// With WAVE the sites address wavefront check tiles: those of this compute
+// tile are kept with row/col converted to the compute tile (sites outside
+// their check tile are dropped) and tile_m/tile_n left as given.
+template <class G, bool WAVE = false>
 __device__ void gather_faults(CheckLds<G>& s, const LaunchArgs& a, const Thread& th) {
     if (th.tid == 0) s.nf = 0;
     __syncthreads();
     for (int q = th.tid; q < a.n_faults; q += G::NT) {
-        const ftgemm_fault_t f = a.faults[q];
-        if (f.problem == a.problem && f.tile_m == th.tm && f.tile_n == th.tn) {
+        ftgemm_fault_t f = a.faults[q];
+        bool mine = f.problem == a.problem;
+        if constexpr (WAVE) {
+            mine = mine && f.tile_m / G::WM == th.tm && f.tile_n / G::WN == th.tn && f.row < G::TM && f.col < G::TN;
+            f.row += (f.tile_m % G::WM) * G::TM;
+            f.col += (f.tile_n % G::WN) * G::TN;
+        } else {
+            mine = mine && f.tile_m == th.tm && f.tile_n == th.tn;
+        }
+        if (mine) {
             const int x = atomicAdd(&s.nf, 1);
             if (x < kMaxFaultsPerTile) { s.fault[x] = f; s.fslot[x] = -1; }
         }
@@ -226,7 +249,7 @@ __device__ void gather_faults(CheckLds<G>& s, const LaunchArgs& a, const Thread&
 
 // Faults of k-step t hit the accumulator (after that step's update): the
 // element is found with uniform block branches and per-lane selects.
-template <class G>
+template <class G, bool WAVE = false>
 __device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th,
                                        int t, int& fnext) {
     while (fnext < s.nf && s.fault[fnext].kstep == t) {
@@ -260,6 +283,10 @@ __device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const Launch
                 ftgemm_fault_log_t L;
                 L.problem = a.problem; L.tile_m = th.tm; L.tile_n = th.tn; L.kstep = t;
                 L.row = f.row; L.col = f.col; L.kind = f.kind; L.check_step = -1;
+                if constexpr (WAVE) {   // back to check-tile coordinates
+                    L.tile_m = f.tile_m; L.tile_n = f.tile_n;
+                    L.row = f.row % G::TM; L.col = f.col % G::TN;
+                }
                 L.old_v = oldv; L.new_v = newv;
                 L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
                 L.pad0_ = L.pad1_ = 0.f;
@@ -281,17 +308,16 @@ __device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const Launch
 // barrier after the census (callers use it as the end-of-step barrier).
 // A check that leaves the tile possibly wrong (any flag at the detect-only
 // level, an uncorrectable pattern at the online level) sets s.tainted.
-template <class G, int FT, bool INJ>
-__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
-                      float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
-    constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
+// One pass over the accumulator, one 32-column block at a time: per-lane
+// partial row sums (over the lane's columns) and the block's column sums over
+// this wave's rows; the 16 column sums of a lane are reduce-scattered over the
+// 32 lanes of its half, leaving lane pair (2x, 2x+1) with entry x.  Leaves
+// s.rowpart[wn][i] = sum of row i over wave column wn's columns and
+// s.colpart[wm][j] = sum of column j over wave row wm's rows (no barrier).
+template <class G>
+__device__ __forceinline__ void tile_sums(const Acc<G>& acc, CheckLds<G>& s, const Thread& th) {
+    constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN;
     const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
-
-    // (1) one pass over the accumulator, one 32-column block at a time:
-    // per-lane partial row sums (over the lane's columns) and the block's
-    // column sums over this wave's rows; the 16 column sums of a lane are
-    // reduce-scattered over the 32 lanes of its half, leaving lane pair
-    // (2x, 2x+1) with entry x.
     float rpart[MI];
 #pragma unroll
     for (int bi = 0; bi < MI; ++bi) rpart[bi] = 0.f;
@@ -323,6 +349,16 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         const float rs = swap_add<5>(rpart[bi], rpart[bi]);
         if (hh == 0) s.rowpart[wn][wm * TM + 32 * bi + l32] = rs;
     }
+}
+
+template <class G, int FT, bool INJ>
+__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
+                      float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
+    constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
+    const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
+
+    // (1) row sums per wave column and column sums per wave row
+    tile_sums<G>(acc, s, th);
     // (2) per-wave sums of the row and column norms for the threshold
     const float na = (th.my_row >= 0) ? sqrtf(na2) : 0.f;
     const float nb = (th.my_col >= 0) ? sqrtf(nb2) : 0.f;
@@ -492,6 +528,212 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         }
         if (th.tid == 0 && (kind == FTGEMM_EV_DETECTED || kind == FTGEMM_EV_UNCORRECTABLE)) s.tainted = 1;
     }
+}
+
+// ---------------------------------------------------------------------------
+// wavefront-tile check (warp-level ABFT, section 4.2.2): every wavefront's
+// TM x TN sub-tile is a check tile with its own encodings and reference
+// checksums, so one fault per wavefront tile and check interval is corrected
+// ---------------------------------------------------------------------------
+// Decision, correction and event of wave (wm, wn)'s own check tile (some
+// row or column flagged; census values in compute-tile coordinates).
+template <class G, int FT>
+__device__ __forceinline__ void own_tile_outcome(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a,
+                                                 const Thread& th, int t, int nr, int ncl, int fr, int fc) {
+    constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN;
+    const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
+    const bool online = (FT == 2) || a.ft_level == 2;
+    const float* b = s.bw[wm + WM * wn];
+    auto event = [&](int kind) {
+        ftgemm_event_t E;
+        E.problem = a.problem; E.tile_m = th.tm * WM + wm; E.tile_n = th.tn * WN + wn; E.kstep = t;
+        E.row = fr >= 0 ? fr - wm * TM : -1; E.col = fc >= 0 ? fc - wn * TN : -1;
+        E.kind = kind; E.n_rows = nr; E.n_cols = ncl; E.pad_ = 0;
+        E.value_before = E.value_after = 0.f;
+        E.r_row = fr >= 0 ? b[1] : 0.f; E.tau_row = fr >= 0 ? b[2] : 0.f;
+        E.r_col = fc >= 0 ? b[3] : 0.f; E.tau_col = fc >= 0 ? b[4] : 0.f;
+        return E;
+    };
+    if (online && nr == 1 && ncl == 1) {
+        // P_ij = R_i - sum_{j' != j} P_ij' within the wave tile
+        const int fbi = (fr % TM) / 32, fjr = fc % TN;
+        const int fbj = fjr / 32, fjj = fjr % 32;
+        const int freg = ((fjj >> 3) << 2) | (fjj & 3);
+        const bool row_lane = l32 == (fr & 31);
+        const bool own = row_lane && hh == ((fjj >> 2) & 1);
+        float part = 0.f, oldv = 0.f;
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi) {
+            if (bi == fbi) {
+#pragma unroll
+                for (int bj = 0; bj < NI; ++bj)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float x = acc[bi][bj][r];
+                        const bool hit = own && bj == fbj && r == freg;
+                        part += hit ? 0.f : x;
+                        oldv = hit ? x : oldv;
+                    }
+            }
+        }
+        part = row_lane ? part : 0.f;
+        part = swap_add<5>(part, part);
+        const float newv = b[0] - part;
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NI; ++bj) {
+                if (bi == fbi && bj == fbj) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[bi][bj][r] = (own && r == freg) ? newv : acc[bi][bj][r];
+                }
+            }
+        if (own) {
+            const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+            atomicAdd(&a.counters[CNT_DETECTED], 1u);
+            atomicAdd(&a.counters[CNT_CORRECTED], 1u);
+            if ((int)e < a.event_cap) {
+                ftgemm_event_t E = event(FTGEMM_EV_CORRECTED);
+                E.value_before = oldv; E.value_after = newv;
+                a.events[e] = E;
+            }
+        }
+    } else {
+        const int kind = !online ? FTGEMM_EV_DETECTED
+                       : (nr == 1 && ncl == 0) ? FTGEMM_EV_CHECKSUM_ROW
+                       : (nr == 0 && ncl == 1) ? FTGEMM_EV_CHECKSUM_COL
+                       : FTGEMM_EV_UNCORRECTABLE;
+        if (lane == 0) {
+            const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+            atomicAdd(&a.counters[CNT_DETECTED], 1u);
+            if (kind == FTGEMM_EV_UNCORRECTABLE) atomicAdd(&a.counters[CNT_UNCORRECTABLE], 1u);
+            if (kind == FTGEMM_EV_CHECKSUM_ROW || kind == FTGEMM_EV_CHECKSUM_COL)
+                atomicAdd(&a.counters[CNT_CHECKSUM_ONLY], 1u);
+            if ((int)e < a.event_cap) a.events[e] = event(kind);
+            if (kind == FTGEMM_EV_DETECTED || kind == FTGEMM_EV_UNCORRECTABLE) s.tainted = 1;
+        }
+    }
+}
+
+// Owner geometry SPLIT: the row owner of tile row i keeps ref[q] = R_i of
+// wave column q (q < WN), the column owner of tile column j keeps ref[q] =
+// S_j of wave row q (q < WM); nrm2 is the owner's ||a_i||^2 or ||b_j||^2.
+// Decisions, re-basing and events are per check tile, with the event's
+// tile_m/tile_n counting check tiles of C and row/col relative to it.  Ends
+// with a workgroup barrier.
+template <class G, int FT, bool INJ, int NR>
+__device__ void check_wave(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
+                           float (&ref)[NR], float nrm2, int fnext, int& flogged) {
+    constexpr int TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
+    constexpr int RW = G::BM / 64;                  // waves 0 .. RW-1 own rows, the others columns
+    constexpr int WPM = TM / 64, WPN = TN / 64;     // owner waves per wave row / wave column
+    static_assert(G::SPLIT && TM % 64 == 0 && TN % 64 == 0 && NR == WaveCheckLds<G>::NR, "wavefront check geometry");
+    const int lane = th.lane, wm = th.wm, wn = th.wn, wave = th.wave;
+    const bool row_role = th.row_role;
+    const int cnt = row_role ? WN : WM;             // check tiles the owner's line crosses
+
+    // (1) sums over each wave tile, (2) per-wave norm sums
+    tile_sums<G>(acc, s, th);
+    const bool owner = th.my_row >= 0 || th.my_col >= 0;
+    const float nv = owner ? sqrtf(nrm2) : 0.f;
+    const float wnv = wave_sum(nv);
+    if (lane == 0) s.nsum[0][wave] = wnv;
+    __syncthreads();
+
+    // (3) residual and threshold against crossed check tile q; recomputed
+    // from LDS where needed again (the sums stay valid until the next check),
+    // so only the flag bits stay in registers
+    const float base = a.tol_c * 2.0f * kUnitRoundoff;
+    const int mine = row_role ? th.my_row : th.my_col;
+    const bool in_range = row_role ? (th.my_row >= 0 && th.my_row < th.mI) : (th.my_col >= 0 && th.my_col < th.nJ);
+    auto residual = [&](int q, float& res, float& tau) -> bool {
+        const int ext = row_role ? th.nJ - q * TN : th.mI - q * TM;   // valid extent of the crossed tile
+        if (!(q < cnt && in_range && ext > 0)) { res = tau = 0.f; return false; }
+        float other_r = 0.f, other_c = 0.f;   // sums of the other side's norms over the crossed tile
+#pragma unroll
+        for (int w = 0; w < WPN; ++w) other_r += s.nsum[0][RW + q * WPN + w];
+#pragma unroll
+        for (int w = 0; w < WPM; ++w) other_c += s.nsum[0][q * WPM + w];
+        const float other = row_role ? other_r : other_c;
+        const float x = row_role ? s.rowpart[q][mine] : s.colpart[q][mine];
+        res = x - ref[q];
+        tau = base * (float)(kp + min(ext, row_role ? TN : TM) + 1) * nv * other;
+        return !(fabsf(res) <= tau);
+    };
+    unsigned flags = 0;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        float res, tau;
+        const bool f = residual(q, res, tau);
+        flags |= f ? (1u << q) : 0u;
+        // owners are in index order within a wave (one line per thread,
+        // tid order): the first flagged line is the lowest flagged lane's
+        const unsigned long long b = __ballot(f);
+        const int first = b ? __builtin_amdgcn_readlane(mine, (int)__builtin_ctzll(b)) : -1;
+        any = any || b != 0;
+        if (lane == 0) { s.wcen[wave][q][0] = __popcll(b); s.wcen[wave][q][1] = first; }
+    }
+    if (lane == 0) s.wany[wave] = any ? 1 : 0;
+    if constexpr (INJ) {   // complete the fault log entries this check is the first to see
+        for (int q = flogged; q < fnext; ++q) {
+            const int slot = s.fslot[q];
+            if (slot < 0 || slot >= a.fault_log_cap) continue;
+            const int fr_ = s.fault[q].row, fc_ = s.fault[q].col;
+            const bool mine_f = row_role ? th.my_row == fr_ : th.my_col == fc_;
+            if (mine_f) {
+                float rq = 0.f, tq = 0.f;
+                (void)residual(row_role ? fc_ / TN : fr_ / TM, rq, tq);
+                if (row_role) { a.fault_log[slot].r_row = rq; a.fault_log[slot].tau_row = tq; }
+                else { a.fault_log[slot].r_col = rq; a.fault_log[slot].tau_col = tq; }
+            }
+            if (th.tid == 0) a.fault_log[slot].check_step = t;
+        }
+        flogged = fnext;
+    }
+    __syncthreads();
+
+    int nany = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) nany += s.wany[w];
+    if (nany == 0) return;
+
+    // rare path (uniform branch): each wave takes the census of its own
+    // check tile and publishes it
+    int nr = 0, ncl = 0, fr = -1, fc = -1;
+    for (int w = 0; w < WPM; ++w) {
+        const int* e = s.wcen[wm * WPM + w][wn];
+        nr += e[0];
+        if (e[1] >= 0 && (fr < 0 || e[1] < fr)) fr = e[1];
+    }
+    for (int w = 0; w < WPN; ++w) {
+        const int* e = s.wcen[RW + wn * WPN + w][wm];
+        ncl += e[0];
+        if (e[1] >= 0 && (fc < 0 || e[1] < fc)) fc = e[1];
+    }
+    if (lane == 0) { s.tdec[wave][0] = nr; s.tdec[wave][1] = ncl; s.tdec[wave][2] = fr; s.tdec[wave][3] = fc; }
+    __syncthreads();
+    // the owners of each check tile's first flagged row and column publish
+    // their values; flagged checksums of tiles that are not corrected are
+    // re-based on the accumulator (online level)
+    const bool online = (FT == 2) || a.ft_level == 2;
+    const int line_tile = row_role ? mine / TM : mine / TN;   // own wave row / column index of the owner's line
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (flags & (1u << q)) {
+            float res, tau;
+            (void)residual(q, res, tau);
+            const int ct = row_role ? line_tile + WM * q : q + WM * line_tile;
+            const int* d = s.tdec[ct];
+            float* b = s.bw[ct];
+            if (row_role && mine == d[2]) { b[0] = ref[q]; b[1] = res; b[2] = tau; }
+            if (!row_role && mine == d[3]) { b[3] = res; b[4] = tau; }
+            if (online && !(d[0] == 1 && d[1] == 1)) ref[q] += res;
+        }
+    }
+    __syncthreads();
+    if (nr + ncl > 0) own_tile_outcome<G, FT>(acc, s, a, th, t, nr, ncl, fr, fc);
+    __syncthreads();   // s.tainted is read by every wave at the end of the tile
 }
 
 // ---------------------------------------------------------------------------

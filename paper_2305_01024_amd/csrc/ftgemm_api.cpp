@@ -85,30 +85,42 @@ int variant_count(int dtype) {
 Variant variant_at(int dtype, int v) {
     return dtype == FTGEMM_BF16 ? bf16_variant(v) : dtype == FTGEMM_F8E4M3 ? fp8_variant(v) : fp32_variant(v);
 }
-int find_variant(int dtype, const ftgemm_config_t& c) {
-    return dtype == FTGEMM_BF16     ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step)
-           : dtype == FTGEMM_F8E4M3 ? fp8_find_variant(c.m_tile, c.n_tile, c.k_step)
-                                    : fp32_find_variant(c.m_tile, c.n_tile, c.k_step);
+// A check shape of 0 stands for the compute tile's.
+ftgemm_config_t normalized(ftgemm_config_t c) {
+    if (c.check_m == 0) c.check_m = c.m_tile;
+    if (c.check_n == 0) c.check_n = c.n_tile;
+    return c;
 }
+int find_variant(int dtype, const ftgemm_config_t& c0) {
+    const ftgemm_config_t c = normalized(c0);
+    return dtype == FTGEMM_BF16     ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
+           : dtype == FTGEMM_F8E4M3 ? fp8_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
+                                    : fp32_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n);
+}
+bool compute_tile_check(const Variant& x) { return x.check_m == x.m_tile && x.check_n == x.n_tile; }
 bool dtype_supported(int dtype) {
     return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3;
 }
 
-// Largest compiled tile that still gives every compute unit a workgroup,
-// else the smallest tile; a check every 256 k.
+// Largest compiled tile (with compute-tile checks) that still gives every
+// compute unit a workgroup, else the smallest tile; a check every 256 k.
 int select_variant(int dtype, int64_t m, int64_t n, ftgemm_config_t* out) {
     const int nv = variant_count(dtype);
-    int pick = nv - 1;
+    int pick = -1;
     for (int v = 0; v < nv; ++v) {
         const Variant x = variant_at(dtype, v);
+        if (!compute_tile_check(x)) continue;
+        pick = v;
         const int64_t tiles = ((m + x.m_tile - 1) / x.m_tile) * ((n + x.n_tile - 1) / x.n_tile);
-        if (tiles >= kNumCUs) { pick = v; break; }
+        if (tiles >= kNumCUs) break;
     }
     const Variant x = variant_at(dtype, pick);
     out->m_tile = x.m_tile;
     out->n_tile = x.n_tile;
     out->k_step = x.k_step;
     out->check_interval = default_interval(x.k_step);
+    out->check_m = x.check_m;
+    out->check_n = x.check_n;
     return FTGEMM_OK;
 }
 
@@ -174,7 +186,7 @@ int grow(T** buf, int* cap, int need) {
 // cost-ordered (problem, tile) list.
 int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
     std::vector<BatchProblem> bp((size_t)count);
-    std::vector<ftgemm_config_t> cfgs((size_t)count, ftgemm_config_t{0, 0, 0, 0});
+    std::vector<ftgemm_config_t> cfgs((size_t)count, ftgemm_config_t{0, 0, 0, 0, 0, 0});
     struct Work { double cost; BatchItem item; };
     std::vector<Work> work;
     uint64_t checks[3] = {0, 0, 0};
@@ -209,7 +221,7 @@ int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
             bm = x.m_tile;
             bn = x.n_tile;
             d.check_interval = default_interval(x.k_step);
-            cfgs[(size_t)p] = {x.m_tile, x.n_tile, x.k_step, d.check_interval};
+            cfgs[(size_t)p] = {x.m_tile, x.n_tile, x.k_step, d.check_interval, x.check_m, x.check_n};
             const int64_t nk = (q.k + x.k_step - 1) / x.k_step;
             per_tile = (double)bm * bn * (double)(nk * x.k_step) / h->batch_rate[d.variant];
             const int64_t tiles = ((q.m + bm - 1) / bm) * ((q.n + bn - 1) / bn);
@@ -371,9 +383,9 @@ int ftgemm_set_config(ftgemm_t h, const ftgemm_config_t* c) {
         h->forced = false;
         return FTGEMM_OK;
     }
-    if (c->check_interval < 1) return FTGEMM_INVALID;
+    if (c->check_interval < 1 || c->check_m < 0 || c->check_n < 0) return FTGEMM_INVALID;
     if (find_variant(h->dtype, *c) < 0) return FTGEMM_UNSUPPORTED;
-    h->cfg = *c;
+    h->cfg = normalized(*c);
     h->forced = true;
     return FTGEMM_OK;
 }
@@ -517,7 +529,9 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
     const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
                            : ft_level == 1 ? 1 : 0;
-    return fill_report(h, stream, report, (uint64_t)(ntiles * per_tile), recompute);
+    // check tiles that hold part of C (a wavefront tile past the edge is not checked)
+    const int64_t nchk = ((m + cfg.check_m - 1) / cfg.check_m) * ((n + cfg.check_n - 1) / cfg.check_n);
+    return fill_report(h, stream, report, (uint64_t)(nchk * per_tile), recompute);
 }
 
 int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
@@ -634,7 +648,7 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
         FT_HIP(launch_nonfused_chunk(nf, (int)q, (int)k0, (int)k1, stream));
     }
     if (!report) return FTGEMM_OK;
-    report->config = ftgemm_config_t{(int32_t)T, (int32_t)T, (int32_t)ck, 1};
+    report->config = ftgemm_config_t{(int32_t)T, (int32_t)T, (int32_t)ck, 1, (int32_t)T, (int32_t)T};
     return fill_report(h, stream, report, (uint64_t)(ntm * ntn * nchunks));
 }
 
@@ -723,14 +737,17 @@ int ftgemm_get_tuned(ftgemm_t h, ftgemm_tuned_t* out, int cap, int* n) {
 }
 
 int ftgemm_add_tuned(ftgemm_t h, const ftgemm_tuned_t* e) {
-    if (!h || !e || e->ft_level < 0 || e->ft_level > 2 || e->config.check_interval < 1) return FTGEMM_INVALID;
+    if (!h || !e || e->ft_level < 0 || e->ft_level > 2 || e->config.check_interval < 1 || e->config.check_m < 0 ||
+        e->config.check_n < 0)
+        return FTGEMM_INVALID;
     if (find_variant(h->dtype, e->config) < 0) return FTGEMM_UNSUPPORTED;
     for (ftgemm_tuned_t& t : h->tuned)
         if (t.m == e->m && t.n == e->n && t.k == e->k && t.ft_level == e->ft_level) {
-            t.config = e->config;
+            t.config = normalized(e->config);
             return FTGEMM_OK;
         }
     h->tuned.push_back(*e);
+    h->tuned.back().config = normalized(e->config);
     return FTGEMM_OK;
 }
 
@@ -759,15 +776,17 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
                hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         st = FTGEMM_HIP_ERROR;
     } else {
-        // candidates: every variant with check intervals 1, 2, 4, ... within the cap
+        // candidates: every variant with check intervals 1, 2, 4, ... within the
+        // cap (at level 0 only the compute-tile variants: the others run the same kernel)
         std::vector<ftgemm_config_t> cand;
         const int nv = variant_count(h->dtype);
         for (int v = 0; v < nv; ++v) {
             const Variant x = variant_at(h->dtype, v);
+            if (ft_level == 0 && !compute_tile_check(x)) continue;
             const int64_t nk = (k + x.k_step - 1) / x.k_step;
             for (int gi = 1;; gi *= 2) {
                 if (gi > 1 && ((int64_t)gi * x.k_step > kmax || gi > nk || ft_level != 2)) break;
-                cand.push_back({x.m_tile, x.n_tile, x.k_step, gi});
+                cand.push_back({x.m_tile, x.n_tile, x.k_step, gi, x.check_m, x.check_n});
             }
         }
         ftgemm_config_t dflt;

@@ -22,7 +22,7 @@ union BatchSmem {
     bf16::SmemBF16<128, 128, 64, 2, 2> bf16_128;
 };
 
-constexpr Variant kBatchVariantTable[kBatchVariants] = {{128, 128, 32}, {64, 64, 64}, {128, 128, 64}};
+constexpr Variant kBatchVariantTable[kBatchVariants] = {{128, 128, 32, 128, 128}, {64, 64, 64, 64, 64}, {128, 128, 64, 128, 128}};
 constexpr int kBatchVariantDtype[kBatchVariants] = {FTGEMM_F32, FTGEMM_F32, FTGEMM_BF16};
 
 // C = beta * C on one 128 x 128 tile (problems with k == 0 or alpha == 0)

@@ -48,17 +48,19 @@ hipError_t launch_shape_bf16(bool inject, const LaunchArgs& a, hipStream_t s) {
 }
 
 constexpr Variant kVariantsBF16[] = {
-    {256, 256, 64},
+    {256, 256, 64, 256, 256},
 };
 
 }  // namespace
 
 int bf16_variant_count() { return sizeof(kVariantsBF16) / sizeof(kVariantsBF16[0]); }
 Variant bf16_variant(int idx) { return kVariantsBF16[idx]; }
-int bf16_find_variant(int m_tile, int n_tile, int k_step) {
+int bf16_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
     for (int v = 0; v < bf16_variant_count(); ++v) {
         const Variant& x = kVariantsBF16[v];
-        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step) return v;
+        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step && x.check_m == check_m &&
+            x.check_n == check_n)
+            return v;
     }
     return -1;
 }

@@ -5,19 +5,20 @@
 namespace ftgemm_impl {
 namespace {
 
-template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
+// WAVE: wavefront-tile checks (FT levels only)
+template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ, bool WAVE = false>
 __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) {
-    __shared__ f32::Smem<BM, BN, BK, WM, WN> sm;
+    __shared__ f32::Smem<BM, BN, BK, WM, WN, WAVE> sm;
     const int ntm = (a.M + BM - 1) / BM;
-    f32::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
+    f32::tile<BM, BN, BK, WM, WN, FT, INJ, WAVE>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
 }
 
 // Recomputes the tiles a launch of the same variant queued (FT levels only).
-template <int BM, int BN, int BK, int WM, int WN, int FT>
+template <int BM, int BN, int BK, int WM, int WN, int FT, bool WAVE = false>
 __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_retry_kernel(LaunchArgs a) {
-    __shared__ f32::Smem<BM, BN, BK, WM, WN> sm;
+    __shared__ f32::Smem<BM, BN, BK, WM, WN, WAVE> sm;
     const int ntm = (a.M + BM - 1) / BM;
-    abft::retry_queue(a, ntm, [&](int tm, int tn) { f32::tile<BM, BN, BK, WM, WN, FT, false>(a, tm, tn, sm); });
+    abft::retry_queue(a, ntm, [&](int tm, int tn) { f32::tile<BM, BN, BK, WM, WN, FT, false, WAVE>(a, tm, tn, sm); });
 }
 
 __global__ void scale_kernel(float* C, int64_t ldc, int32_t M, int32_t N, float beta) {
@@ -33,54 +34,59 @@ __global__ void scale_kernel(float* C, int64_t ldc, int32_t M, int32_t N, float 
 // ---------------------------------------------------------------------------
 // variant table
 // ---------------------------------------------------------------------------
-struct VariantDef {
-    Variant v;
-    int wm, wn;
-};
-constexpr VariantDef kVariants[] = {
-    {{256, 256, 32}, 2, 4},
-    {{256, 128, 32}, 2, 2},
-    {{128, 256, 32}, 1, 4},
-    {{128, 128, 32}, 2, 2},
-    {{64, 64, 32}, 1, 1},
+// compute-tile checks first (automatic selection walks them in order), then
+// the wavefront-tile check (check tile = one wave's 64 x 64 sub-tile).  The
+// 256 x 256 tile has no wavefront-check variant: its 8 wavefronts hold 128
+// accumulators each at two wavefronts per SIMD, and the four reference
+// checksums per row owner do not fit beside them without spilling.
+constexpr Variant kVariants[] = {
+    {256, 256, 32, 256, 256},
+    {256, 128, 32, 256, 128},
+    {128, 256, 32, 128, 256},
+    {128, 128, 32, 128, 128},
+    {64, 64, 32, 64, 64},
+    {128, 128, 32, 64, 64},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int BM, int BN, int BK, int WM, int WN>
+// Level 0 of a wavefront-check variant runs the plain kernel of its tile.
+template <int BM, int BN, int BK, int WM, int WN, bool WAVE = false>
 hipError_t launch_shape(bool inject, const LaunchArgs& a, hipStream_t s) {
     const int ntm = (a.M + BM - 1) / BM, ntn = (a.N + BN - 1) / BN;
     const dim3 grid((unsigned)(ntm * ntn)), block(64 * WM * WN);
-#define FTGEMM_LAUNCH(FTL, INJL) \
-    hipLaunchKernelGGL((ftgemm_f32_kernel<BM, BN, BK, WM, WN, FTL, INJL>), grid, block, 0, s, a)
+#define FTGEMM_LAUNCH(FTL, INJL, WV) \
+    hipLaunchKernelGGL((ftgemm_f32_kernel<BM, BN, BK, WM, WN, FTL, INJL, WV>), grid, block, 0, s, a)
     if (inject) {
-        if (a.ft_level == 0) FTGEMM_LAUNCH(0, true);
-        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, true);
-        else FTGEMM_LAUNCH(2, true);
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, true, false);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, true, WAVE);
+        else FTGEMM_LAUNCH(2, true, WAVE);
     } else {
-        if (a.ft_level == 0) FTGEMM_LAUNCH(0, false);
-        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, false);
-        else FTGEMM_LAUNCH(2, false);
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, false, false);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, false, WAVE);
+        else FTGEMM_LAUNCH(2, false, WAVE);
     }
 #undef FTGEMM_LAUNCH
     return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool WAVE = false>
 hipError_t launch_shape_retry(const LaunchArgs& a, int grid, hipStream_t s) {
     const dim3 g((unsigned)grid), block(64 * WM * WN);
-    if (a.ft_level == 1) hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 1>), g, block, 0, s, a);
-    else hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 2>), g, block, 0, s, a);
+    if (a.ft_level == 1) hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 1, WAVE>), g, block, 0, s, a);
+    else hipLaunchKernelGGL((ftgemm_f32_retry_kernel<BM, BN, BK, WM, WN, 2, WAVE>), g, block, 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
 int fp32_variant_count() { return kNumVariants; }
-Variant fp32_variant(int idx) { return kVariants[idx].v; }
-int fp32_find_variant(int m_tile, int n_tile, int k_step) {
+Variant fp32_variant(int idx) { return kVariants[idx]; }
+int fp32_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
     for (int v = 0; v < kNumVariants; ++v) {
-        const Variant& x = kVariants[v].v;
-        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step) return v;
+        const Variant& x = kVariants[v];
+        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step && x.check_m == check_m &&
+            x.check_n == check_n)
+            return v;
     }
     return -1;
 }
@@ -92,6 +98,7 @@ hipError_t launch_fp32(int idx, bool inject, const LaunchArgs& a, hipStream_t s)
         case 2: return launch_shape<128, 256, 32, 1, 4>(inject, a, s);
         case 3: return launch_shape<128, 128, 32, 2, 2>(inject, a, s);
         case 4: return launch_shape<64, 64, 32, 1, 1>(inject, a, s);
+        case 5: return launch_shape<128, 128, 32, 2, 2, true>(inject, a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -103,6 +110,7 @@ hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t
         case 2: return launch_shape_retry<128, 256, 32, 1, 4>(a, grid, s);
         case 3: return launch_shape_retry<128, 128, 32, 2, 2>(a, grid, s);
         case 4: return launch_shape_retry<64, 64, 32, 1, 1>(a, grid, s);
+        case 5: return launch_shape_retry<128, 128, 32, 2, 2, true>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

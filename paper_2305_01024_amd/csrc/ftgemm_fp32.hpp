@@ -49,32 +49,38 @@ using namespace abft;
 // conflict-free.
 __device__ __forceinline__ constexpr int aswz(int i) { return (i >> 4) & 3; }
 
-template <int BM, int BN, int BK>
+// EA / EB: encodings per panel (1 for compute-tile checks; WM / WN for
+// wavefront-tile checks, one per wave row / wave column of the tile).
+template <int BM, int BN, int BK, int EA = 1, int EB = 1>
 struct alignas(16) Operands {   // 16-byte aligned: the panel reads are 16-byte LDS loads
     static constexpr int KP = BK + 4;   // row pitch: conflict-free 16-byte reads by 16 lanes on 16 rows
     float As[2][BM][KP];        // A panel, i-major (k contiguous)
     float Bs[2][BN][KP];        // B panel, j-major (k contiguous)
-    float wsum[2][BK];          // e^T A of the panel, per k
-    float vsum[3][BK];          // B e of the panel, per k (accumulated across waves, 3 rotating slots)
+    float wsum[2][EA][BK];      // e^T A of the panel (per wave row group), per k
+    float vsum[3][EB][BK];      // B e of the panel (per wave column group), per k (accumulated across waves, 3 rotating slots)
     float dummy[256];           // sink for the stores/atomics of lanes that own no value
 };
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool WAVE = false>
 struct Smem {
-    Operands<BM, BN, BK> op;
-    CheckLds<Geometry<BM, BN, WM, WN>> ck;
+    using G = Geometry<BM, BN, WM, WN>;
+    Operands<BM, BN, BK, WAVE ? WM : 1, WAVE ? WN : 1> op;
+    std::conditional_t<WAVE, WaveCheckLds<G>, CheckLds<G>> ck;
 };
 
 // ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 // One BM x BN output tile (tm, tn) of the problem in `a`, computed by one
-// workgroup of 64 * WM * WN threads with `sm` as its LDS.
-template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
-__device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<BM, BN, BK, WM, WN>& sm) {
+// workgroup of 64 * WM * WN threads with `sm` as its LDS.  WAVE: each
+// wavefront's TM x TN sub-tile is a check tile (warp-level ABFT, section
+// 4.2.2) instead of the whole tile (section 4.2.3).
+template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ, bool WAVE = false>
+__device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<BM, BN, BK, WM, WN, WAVE>& sm) {
     using G = Geometry<BM, BN, WM, WN>;
     constexpr int NT = G::NT, TM = G::TM, TN = G::TN, MI = G::MI, NI = G::NI;
     constexpr int KP = Operands<BM, BN, BK>::KP;
+    constexpr int EA = WAVE ? WM : 1, EB = WAVE ? WN : 1;
     constexpr int AIQ = BM / 4;                // i-quads of the A panel
     constexpr int NA = BM * BK / (16 * NT);    // 4 x 4 blocks of A per thread
     constexpr int NB = BN * BK / (4 * NT);     // float4 slots of B per thread
@@ -86,8 +92,10 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     static_assert(BM * BK == 16 * NA * NT && (AIQ % 64 == 0 || 64 % AIQ == 0), "A block mapping");
     static_assert(LNA <= LAG, "encode reduce-scatter needs 4 NA <= AG");
     static_assert(NT % BKQ == 0 && 64 % BKQ == 0 && BKQ <= 16, "B slot mapping");
+    static_assert(!WAVE || (G::SPLIT && TN % (NT / BKQ) == 0 && TM / 4 <= AG && NT >= EB * BK),
+                  "wavefront checks: one owner per line, each B slot inside one wave column");
 
-    Operands<BM, BN, BK>& op = sm.op;
+    auto& op = sm.op;
 
     const Thread th = make_thread<G>(a, tm, tn);
     const int tid = th.tid, lane = th.lane, wm = th.wm, wn = th.wn, l32 = th.l32, hh = th.hh;
@@ -98,11 +106,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     const bool alignB = ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0) && ((a.ldb & 3) == 0);
 
     if constexpr (FT > 0) {
-        for (int x = tid; x < 3 * BK; x += NT) (&op.vsum[0][0])[x] = 0.f;
+        for (int x = tid; x < 3 * EB * BK; x += NT) (&op.vsum[0][0][0])[x] = 0.f;
         if (tid == 0) sm.ck.tainted = 0;
     }
     int fnext = 0, flogged = 0;
-    if constexpr (INJ) gather_faults<G>(sm.ck, a, th);
+    if constexpr (INJ) gather_faults<G, WAVE>(sm.ck, a, th);
     __syncthreads();
 
     // ---- global -> register staging of one k-step's panels ----
@@ -214,7 +222,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
 #pragma unroll
             for (int e = 0; e < 4; ++e) ws[4 * r + e] = (ra[r][e][0] + ra[r][e][1]) + (ra[r][e][2] + ra[r][e][3]);
         }
-        if constexpr (FT > 0) {
+        if constexpr (FT > 0 && !WAVE) {
             // e^T A: the AG lanes of one k-quad group (lane bits 0 .. LAG-1)
             // hold all BM rows of their k-quads; one reduce-scatter over those
             // bits leaves entry v = (lane >> (LAG - LNA)) of the 4 NA sums in
@@ -223,7 +231,20 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
             const int v = (lane >> (LAG - LNA)) & (4 * NA - 1);
             const int f = tid - (lane & (AG - 1)) + NT * (v >> 2);
             const int kk = 4 * (f / AIQ) + (v & 3);
-            float* dst = ((lane & ((1 << (LAG - LNA)) - 1)) == 0) ? &op.wsum[buf][kk] : &op.dummy[lane];
+            float* dst = ((lane & ((1 << (LAG - LNA)) - 1)) == 0) ? &op.wsum[buf][0][kk] : &op.dummy[lane];
+            *dst = ws[0];
+        } else if constexpr (FT > 0) {
+            // e^T A_w per wave row group: the same reduce-scatter over the AW
+            // lanes that hold one group's TM rows of a k-quad (lane bits
+            // 0 .. LAW-1)
+            constexpr int AW = TM / 4, LAW = ilog2(AW);
+            static_assert(LNA <= LAW, "encode reduce-scatter needs 4 NA <= AW");
+            ReduceScatter<4 * NA, LAW - 1, 0>::run(ws, lane);
+            const int v = (lane >> (LAW - LNA)) & (4 * NA - 1);
+            const int f = tid - (lane & (AW - 1)) + NT * (v >> 2);
+            const int kk = 4 * (f / AIQ) + (v & 3);
+            const int grp = 4 * (f % AIQ) / TM;
+            float* dst = ((lane & ((1 << (LAW - LNA)) - 1)) == 0) ? &op.wsum[buf][grp][kk] : &op.dummy[lane];
             *dst = ws[0];
         }
     };
@@ -234,17 +255,31 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
             const int f = tid + NT * r;
             const int kq = f % BKQ, jj = f / BKQ;
             *reinterpret_cast<f32x4*>(&op.Bs[buf][jj][4 * kq]) = rb[r];
-            vp += rb[r];
+            if constexpr (!WAVE) vp += rb[r];
         }
-        if constexpr (FT > 0) {
-            // B e: the 4 k of k-quad (lane % BKQ) are summed over the lanes of
-            // that quad (bits log2(BKQ)..5); lane keeps k = 4 (lane % BKQ) +
-            // ((lane >> 4) & 3); waves then add their partials in LDS.
+        // B e: the 4 k of k-quad (lane % BKQ) are summed over the lanes of
+        // that quad (bits log2(BKQ)..5); lane keeps k = 4 (lane % BKQ) +
+        // ((lane >> 4) & 3); waves then add their partials in LDS.
+        if constexpr (FT > 0 && !WAVE) {
             float vx[4] = {vp[0], vp[1], vp[2], vp[3]};
             ReduceScatter<4, 5, ilog2(BKQ)>::run(vx, lane);
             const int kv = 4 * (lane % BKQ) + ((lane >> 4) & 3);
-            float* dst = ((lane & (16 - BKQ)) == 0) ? &op.vsum[vslot][kv] : &op.dummy[lane];
+            float* dst = ((lane & (16 - BKQ)) == 0) ? &op.vsum[vslot][0][kv] : &op.dummy[lane];
             atomicAdd(dst, vx[0]);
+        } else if constexpr (FT > 0) {
+            // B_w e per wave column group q (slot r lies in group (NT r / BKQ) / TN)
+#pragma unroll
+            for (int q = 0; q < EB; ++q) {
+                f32x4 vq = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+                    if ((NT * r / BKQ) / TN == q) vq += rb[r];
+                float vx[4] = {vq[0], vq[1], vq[2], vq[3]};
+                ReduceScatter<4, 5, ilog2(BKQ)>::run(vx, lane);
+                const int kv = 4 * (lane % BKQ) + ((lane >> 4) & 3);
+                float* dst = ((lane & (16 - BKQ)) == 0) ? &op.vsum[vslot][q][kv] : &op.dummy[lane];
+                atomicAdd(dst, vx[0]);
+            }
         }
     };
 
@@ -317,22 +352,56 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
     // The operands of a group's update are read before the group's MFMAs (with
     // the next group's fragments) and applied after them, so their LDS
     // latency hides behind the MFMAs instead of stalling the wave.
+    // Wavefront-tile checks: the row owner keeps R against each wave
+    // column's encoding vsum[.][q] (q < WN), the column owner S against each
+    // wave row's wsum[.][q] (q < WM); wref[q] for q beyond the owner's count
+    // is computed and ignored.
+    constexpr int NR = WAVE ? (WM > WN ? WM : WN) : 1;
+    float wref[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) wref[q] = 0.f;
+    // The wavefront-check update runs after the k-step's MFMAs, 4 k at a
+    // time, where the fragment and staging registers are free (the other
+    // wavefront on the SIMD keeps the matrix cores busy meanwhile).
+    struct FtHalf {
+        f32x4 x, y[NR];
+    };
+    auto ft_load_half = [&](int cur, int vcur, int g, int h) {
+        FtHalf o;
+        const float* px = x0_arr + cur * x0_buf + x0_row * KP;
+        o.x = *reinterpret_cast<const f32x4*>(px + 4 * ((2 * g + h) ^ x0_swz));
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const float* py = row_role ? &op.vsum[vcur][q < EB ? q : EB - 1][8 * g + 4 * h]
+                                       : &op.wsum[cur][q < EA ? q : EA - 1][8 * g + 4 * h];
+            o.y[q] = *reinterpret_cast<const f32x4*>(py);
+        }
+        return o;
+    };
+    auto ft_apply_half = [&](const FtHalf& o) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) wref[q] = fmaf(o.x[e], o.y[q][e], wref[q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) nq0 = fmaf(o.x[e], o.x[e], nq0);
+    };
     struct FtOps {
         f32x4 xa, xb, ya, yb, b0, b1, w0, w1;
     };
     auto ft_load = [&](int cur, int vcur, int g) {
         FtOps o;
         const float* px = x0_arr + cur * x0_buf + x0_row * KP;
-        const float* py = row_role ? &op.vsum[vcur][8 * g] : &op.wsum[cur][8 * g];
         o.xa = *reinterpret_cast<const f32x4*>(px + 4 * ((2 * g) ^ x0_swz));
         o.xb = *reinterpret_cast<const f32x4*>(px + 4 * ((2 * g + 1) ^ x0_swz));
+        const float* py = row_role ? &op.vsum[vcur][0][8 * g] : &op.wsum[cur][0][8 * g];
         o.ya = *reinterpret_cast<const f32x4*>(py);
         o.yb = *reinterpret_cast<const f32x4*>(py + 4);
         if constexpr (!SPLIT) {
             o.b0 = *reinterpret_cast<const f32x4*>(&op.Bs[cur][x1_row][8 * g]);
             o.b1 = *reinterpret_cast<const f32x4*>(&op.Bs[cur][x1_row][8 * g + 4]);
-            o.w0 = *reinterpret_cast<const f32x4*>(&op.wsum[cur][8 * g]);
-            o.w1 = *reinterpret_cast<const f32x4*>(&op.wsum[cur][8 * g + 4]);
+            o.w0 = *reinterpret_cast<const f32x4*>(&op.wsum[cur][0][8 * g]);
+            o.w1 = *reinterpret_cast<const f32x4*>(&op.wsum[cur][0][8 * g + 4]);
         }
         return o;
     };
@@ -379,13 +448,13 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
             if constexpr (FT == 0) load_B(t + 1);
         }
         if constexpr (FT > 0 && NEXT)   // slot for step t+2: its last reader finished before this step
-            (&op.vsum[(t + 2) % 3][0])[tid < BK ? tid : BK - 1] = 0.f;
+            (&op.vsum[(t + 2) % 3][0][0])[tid < EB * BK ? tid : EB * BK - 1] = 0.f;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             FtOps o;
-            if constexpr (FT > 0) o = ft_load(cur, t % 3, g);
+            if constexpr (FT > 0 && !WAVE) o = ft_load(cur, t % 3, g);
             mfma_group(cur, g);
-            if constexpr (FT > 0) ft_apply(o);
+            if constexpr (FT > 0 && !WAVE) ft_apply(o);
             if constexpr (NEXT) {
                 if (g == GA) {
                     store_A(cur ^ 1);
@@ -394,16 +463,25 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
                 if (g == GB) store_B(cur ^ 1, (t + 1) % 3);
             }
         }
+        if constexpr (FT > 0 && WAVE) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf) ft_apply_half(ft_load_half(cur, t % 3, g, hf));
+        }
     };
 
     // injection hook and online check after k-step t.  The detect-only level
     // has the same loop: the host sets its check interval beyond the last
     // k-step, so it checks once, after the last step.
     auto post = [&](int t) -> bool {
-        if constexpr (INJ) inject<G>(acc, sm.ck, a, th, t, fnext);
+        if constexpr (INJ) inject<G, WAVE>(acc, sm.ck, a, th, t, fnext);
         bool do_check = false;
         if constexpr (FT > 0) do_check = ((t + 1) % a.check_interval == 0) || (t == nk - 1);
-        if (do_check) check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
+        if (do_check) {
+            if constexpr (WAVE) check_wave<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), wref, nq0, fnext, flogged);
+            else check<G, FT, INJ>(acc, sm.ck, a, th, t, min((t + 1) * BK, a.K), Rr, na2, Sc, nb2, fnext, flogged);
+        }
         return do_check;
     };
 

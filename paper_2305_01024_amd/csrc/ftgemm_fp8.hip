@@ -48,17 +48,19 @@ hipError_t launch_shape_fp8(bool inject, const LaunchArgs& a, hipStream_t s) {
 }
 
 constexpr Variant kVariantsFP8[] = {
-    {256, 256, 64},
+    {256, 256, 64, 256, 256},
 };
 
 }  // namespace
 
 int fp8_variant_count() { return sizeof(kVariantsFP8) / sizeof(kVariantsFP8[0]); }
 Variant fp8_variant(int idx) { return kVariantsFP8[idx]; }
-int fp8_find_variant(int m_tile, int n_tile, int k_step) {
+int fp8_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
     for (int v = 0; v < fp8_variant_count(); ++v) {
         const Variant& x = kVariantsFP8[v];
-        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step) return v;
+        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step && x.check_m == check_m &&
+            x.check_n == check_n)
+            return v;
     }
     return -1;
 }

@@ -53,14 +53,16 @@ struct LaunchArgs {
     int32_t retry_pass;
 };
 
+// A compiled kernel variant: compute tile, k-step and check tile (the
+// compute tile itself, or the sub-tile of one wavefront).
 struct Variant {
-    int m_tile, n_tile, k_step;
+    int m_tile, n_tile, k_step, check_m, check_n;
 };
 
 // Kernel variants compiled for FP32 operands, in preference order.
 int fp32_variant_count();
 Variant fp32_variant(int idx);
-int fp32_find_variant(int m_tile, int n_tile, int k_step);
+int fp32_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 
 // Launch the FP32 kernel variant `idx` (A, B as float).  `inject` selects the instantiation
 // carrying the fault-injection hook.  Returns a hipError_t.
@@ -71,14 +73,14 @@ hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t
 // Kernel variants for BF16 operands (A, B as bfloat16 codes).
 int bf16_variant_count();
 Variant bf16_variant(int idx);
-int bf16_find_variant(int m_tile, int n_tile, int k_step);
+int bf16_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_bf16_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 
 // Kernel variants for FP8 E4M3 operands (A, B as 8-bit codes).
 int fp8_variant_count();
 Variant fp8_variant(int idx);
-int fp8_find_variant(int m_tile, int n_tile, int k_step);
+int fp8_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_fp8_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 

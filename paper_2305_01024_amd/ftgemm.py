@@ -37,11 +37,16 @@ FAULT_LOG_DTYPE = np.dtype([("problem", "<i4"), ("tile_m", "<i4"), ("tile_n", "<
 
 
 class Config(ctypes.Structure):
+    """(m_tile, n_tile, k_step, check_interval, check_m, check_n); a 4-tuple
+    leaves the check shape 0, i.e. the compute tile."""
     _fields_ = [("m_tile", ctypes.c_int32), ("n_tile", ctypes.c_int32), ("k_step", ctypes.c_int32),
-                ("check_interval", ctypes.c_int32)]
+                ("check_interval", ctypes.c_int32), ("check_m", ctypes.c_int32), ("check_n", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.m_tile, self.n_tile, self.k_step, self.check_interval)
+        return (self.m_tile, self.n_tile, self.k_step, self.check_interval, self.check_m, self.check_n)
+
+    def check_shape(self):
+        return (self.check_m or self.m_tile, self.check_n or self.n_tile)
 
 
 class Report(ctypes.Structure):
@@ -244,7 +249,7 @@ def ftgemm_tune(handle: int, m: int, n: int, k: int, ft_level: int = FT_CORRECT,
 
 
 def ftgemm_get_tuned(handle: int) -> list:
-    """The handle's tuned configurations as [(m, n, k, ft_level, (m_tile, n_tile, k_step, g))]."""
+    """The handle's tuned configurations as [(m, n, k, ft_level, Config.as_tuple())]."""
     n = ctypes.c_int(0)
     _check(lib().ftgemm_get_tuned(handle, None, 0, ctypes.byref(n)), "ftgemm_get_tuned")
     buf = (Tuned * max(1, n.value))()

@@ -83,11 +83,20 @@ def _gpu_force(events, inj, check_step) -> int:
     return None
 
 
+def check_cfg(cfg):
+    """(check_m, check_n, k_step, check_interval) of a configuration tuple:
+    the check tile is the compute tile unless a check shape is given."""
+    cm = cfg[4] if len(cfg) > 4 and cfg[4] else cfg[0]
+    cn = cfg[5] if len(cfg) > 5 and cfg[5] else cfg[1]
+    return (cm, cn, cfg[2], cfg[3])
+
+
 def replay_against_gpu(A, B, cfg, rep, log, C0=None, alpha=1.0, beta=0.0, ft_level=2, tiles=None):
     """Replay the run on the oracle with the GPU's applied faults.  Faults the
     oracle classifies grey (either decision is valid) take the GPU's decision;
     returns (ReplayResult, classes of the first pass, n_grey, n_grey_invalid)."""
-    rc = O.ReplayConfig(mc=cfg[0], nc=cfg[1], ku=cfg[2], g=cfg[3], c=float(rep.report.tol_used),
+    cc = check_cfg(cfg)
+    rc = O.ReplayConfig(mc=cc[0], nc=cc[1], ku=cc[2], g=cc[3], c=float(rep.report.tol_used),
                         ft_level=ft_level)
     inj = log_to_injections(log)
     res = O.replay(A, B, rc, C0=C0, alpha=alpha, beta=beta, injections=inj, tiles=tiles)

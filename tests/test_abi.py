@@ -42,10 +42,10 @@ def test_struct_sizes_match_header_layout():
     assert F.EVENT_DTYPE.itemsize == 64
     assert F.FAULT_DTYPE.itemsize == 32
     assert F.FAULT_LOG_DTYPE.itemsize == 64
-    assert ctypes.sizeof(F.Config) == 16
-    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(F.Config) == 24
+    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 24 + 4 + 4 + 4 + 4 + 4 + 4
     assert F.PROBLEM_DTYPE.itemsize == 96
-    assert ctypes.sizeof(F.Tuned) == 48
+    assert ctypes.sizeof(F.Tuned) == 56
     assert W.SITE_DTYPE == F.FAULT_DTYPE
 
 
@@ -139,6 +139,10 @@ def test_select_config_fills_the_gpu_and_checks_every_256_k():
         tiles = -(-m // c.m_tile) * -(-n // c.n_tile)
         assert c.k_step * c.check_interval == 256
         assert tiles >= 256 or (c.m_tile, c.n_tile) == (64, 64), (m, n, c.as_tuple())
+        assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)    # automatic selection: compute-tile checks
+    for dtype in (F.BF16, F.F8E4M3):
+        c = F.ftgemm_select_config(dtype, 8192, 8192, 8192)
+        assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)
     assert F.ftgemm_select_config(F.F32, 8192, 8192, 8192).as_tuple()[:2] == (256, 256)
     assert F.ftgemm_select_config(F.F32, 2048, 2048, 2048).as_tuple()[:2] == (128, 128)
 

@@ -12,7 +12,7 @@ from oracle import oracle as O
 from paper_2305_01024_amd import ftgemm as F
 from paper_2305_01024_amd import workloads as W
 
-from gpu_util import event_keys, rel_fro, replay_against_gpu
+from gpu_util import check_cfg, event_keys, rel_fro, replay_against_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -44,6 +44,7 @@ def operands():
 
 
 def _sample_tiles(m, n, cfg):
+    cfg = check_cfg(cfg)
     ntm, ntn = -(-m // cfg[0]), -(-n // cfg[1])
     pick = {(0, 0), (ntm - 1, ntn - 1), (ntm // 2, ntn // 2), (0, ntn - 1), (ntm - 1, 0)}
     return sorted(pick)
@@ -66,16 +67,18 @@ def _check_tiles(A, B, dC, m, n, cfg, rep, log=None):
         res, cls, n_grey, bad = replay_against_gpu(A, B, cfg, rep, keep, tiles=tiles)
         assert bad == 0
     else:
-        res = O.replay(A, B, O.ReplayConfig(mc=cfg[0], nc=cfg[1], ku=cfg[2], g=cfg[3],
+        cc = check_cfg(cfg)
+        res = O.replay(A, B, O.ReplayConfig(mc=cc[0], nc=cc[1], ku=cc[2], g=cc[3],
                                             c=float(rep.report.tol_used)), tiles=tiles)
     ev = rep.events
     if len(ev):
         ev = ev[np.array([(int(e["tile_m"]), int(e["tile_n"])) in tset for e in ev], dtype=bool)]
     assert event_keys(ev) == event_keys(res.events)
     C = dC.cpu().numpy()
+    cc = check_cfg(cfg)
     for (tm, tn) in tiles:
-        i0, j0 = tm * cfg[0], tn * cfg[1]
-        i1, j1 = min(m, i0 + cfg[0]), min(n, j0 + cfg[1])
+        i0, j0 = tm * cc[0], tn * cc[1]
+        i1, j1 = min(m, i0 + cc[0]), min(n, j0 + cc[1])
         got = C[j0:j1, i0:i1].T
         assert rel_fro(got, res.C[i0:i1, j0:j1]) <= TOL, (tm, tn)
     return res
