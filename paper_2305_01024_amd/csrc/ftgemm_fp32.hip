@@ -5,9 +5,14 @@
 namespace ftgemm_impl {
 namespace {
 
-// WAVE: wavefront-tile checks (FT levels only)
+// WAVE: wavefront-tile checks (FT levels only).  The 128 x 128 tile's LDS
+// (79 KB) leaves room for two workgroups per compute unit; asking for two
+// wavefronts per SIMD holds its FT kernels to 256 VGPRs, which they fit in
+// without spilling in the main loop (the plain kernel is there already).
+template <int BM, int BN, int FT>
+constexpr int kMinWaves = (BM == 128 && BN == 128 && FT > 0) ? 2 : 1;
 template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ, bool WAVE = false>
-__global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(64 * WM * WN, (kMinWaves<BM, BN, FT>)) void ftgemm_f32_kernel(LaunchArgs a) {
     __shared__ f32::Smem<BM, BN, BK, WM, WN, WAVE> sm;
     const int ntm = (a.M + BM - 1) / BM;
     f32::tile<BM, BN, BK, WM, WN, FT, INJ, WAVE>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
