@@ -102,17 +102,54 @@ bool dtype_supported(int dtype) {
     return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3;
 }
 
-// Largest compiled tile (with compute-tile checks) that still gives every
-// compute unit a workgroup, else the smallest tile; a check every 256 k.
-int select_variant(int dtype, int64_t m, int64_t n, ftgemm_config_t* out) {
+// Modelled time of an FP32 variant on an m x n output (the k extent is common
+// to all variants and left out): the tiles run in waves of
+// kNumCUs * wg_per_cu workgroups, and a full wave takes the time its work
+// needs at the variant's full-load rate.  A last, partial wave with fewer
+// wavefronts per SIMD than a full one takes the fraction of a full wave that
+// its wavefronts per SIMD need, but at least kPartialWave (a wavefront that
+// has its SIMD to itself runs faster, not proportionally: a 128x128
+// workgroup alone on a compute unit takes ~0.65 of the time it takes beside
+// another); a 64x64 workgroup is one wavefront, so a partial wave of it
+// still takes a full wave's time.
+double modelled_time(const Variant& x, const VariantModel& mdl, int64_t m, int64_t n, bool ft) {
+    constexpr double kPartialWave = 0.65;
+    constexpr int kSimdsPerCU = 4;
+    const int64_t tiles = ((m + x.m_tile - 1) / x.m_tile) * ((n + x.n_tile - 1) / x.n_tile);
+    const int64_t slots = (int64_t)kNumCUs * mdl.wg_per_cu;
+    const double wave = (double)slots * x.m_tile * x.n_tile / (ft ? mdl.tflops_ft : mdl.tflops_plain);
+    const int64_t full = tiles / slots, rem = tiles - full * slots;
+    double t = (double)full * wave;
+    if (rem > 0) {
+        auto per_simd = [&](int64_t wg_per_cu) {
+            return (wg_per_cu * mdl.waves_per_wg + kSimdsPerCU - 1) / kSimdsPerCU;
+        };
+        const double frac = (double)per_simd((rem + kNumCUs - 1) / kNumCUs) / (double)per_simd(mdl.wg_per_cu);
+        t += wave * std::max(kPartialWave, frac);
+    }
+    return t;
+}
+
+// FP32: the compute-tile variant with the least modelled time (ties: the
+// earlier, larger tile); other dtypes: their first compute-tile variant.  A
+// check every 256 k.
+int select_variant(int dtype, int64_t m, int64_t n, int ft_level, ftgemm_config_t* out) {
     const int nv = variant_count(dtype);
     int pick = -1;
+    double best = 0.0;
     for (int v = 0; v < nv; ++v) {
         const Variant x = variant_at(dtype, v);
         if (!compute_tile_check(x)) continue;
-        pick = v;
-        const int64_t tiles = ((m + x.m_tile - 1) / x.m_tile) * ((n + x.n_tile - 1) / x.n_tile);
-        if (tiles >= kNumCUs) break;
+        if (dtype != FTGEMM_F32) {
+            pick = v;
+            break;
+        }
+        const double t = modelled_time(x, fp32_variant_model(v), std::max<int64_t>(m, 1), std::max<int64_t>(n, 1),
+                                       base_level(ft_level) > 0);
+        if (pick < 0 || t < best * (1.0 - 1e-9)) {
+            pick = v;
+            best = t;
+        }
     }
     const Variant x = variant_at(dtype, pick);
     out->m_tile = x.m_tile;
@@ -314,10 +351,9 @@ int ftgemm_validate(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, i
 
 int ftgemm_select_config(int dtype, int64_t m, int64_t n, int64_t k, int ft_level, ftgemm_config_t* config) {
     (void)k;
-    (void)ft_level;
     if (!config) return FTGEMM_INVALID;
     if (!dtype_supported(dtype)) return FTGEMM_UNSUPPORTED;
-    return select_variant(dtype, m, n, config);
+    return select_variant(dtype, m, n, ft_level, config);
 }
 
 int ftgemm_create(ftgemm_t* handle, int dtype, int device) {
@@ -472,7 +508,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     ft_level = base_level(ft_level);
     ftgemm_config_t cfg;
     if (h->forced) cfg = h->cfg;
-    else if (!find_tuned(h, m, n, k, ft_level, &cfg)) select_variant(h->dtype, m, n, &cfg);
+    else if (!find_tuned(h, m, n, k, ft_level, &cfg)) select_variant(h->dtype, m, n, ft_level, &cfg);
     const int variant = find_variant(h->dtype, cfg);
     if (variant < 0) return FTGEMM_UNSUPPORTED;
     const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
@@ -618,7 +654,7 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
     // the plain kernel for the chunk shape: a configuration tuned for (m, n, chunk) at
     // level 0 if the handle has one, else the default
     ftgemm_config_t cfg;
-    if (!find_tuned(h, m, n, std::min<int64_t>(ck, k), FTGEMM_FT_OFF, &cfg)) select_variant(FTGEMM_F32, m, n, &cfg);
+    if (!find_tuned(h, m, n, std::min<int64_t>(ck, k), FTGEMM_FT_OFF, &cfg)) select_variant(FTGEMM_F32, m, n, FTGEMM_FT_OFF, &cfg);
     const int variant = find_variant(FTGEMM_F32, cfg);
     if (variant < 0) return FTGEMM_UNSUPPORTED;
     LaunchArgs a{};
@@ -790,7 +826,7 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
             }
         }
         ftgemm_config_t dflt;
-        select_variant(h->dtype, m, n, &dflt);
+        select_variant(h->dtype, m, n, ft_level, &dflt);
         if (ft_level == 2)   // the default interval may exceed the cap: clamp it like the candidates
             while (dflt.check_interval > 1 && (int64_t)dflt.check_interval * dflt.k_step > kmax) dflt.check_interval /= 2;
         auto once = [&]() {

@@ -53,6 +53,12 @@ constexpr Variant kVariants[] = {
     {128, 128, 32, 64, 64},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+// aligned with kVariants (the wavefront-check variant is never auto-selected)
+constexpr VariantModel kModels[] = {
+    {1, 8, 137.4f, 123.3f}, {1, 4, 117.4f, 99.1f}, {1, 4, 118.4f, 95.8f}, {2, 4, 137.0f, 113.1f},
+    {4, 1, 111.1f, 81.9f}, {2, 4, 137.0f, 96.2f},
+};
+static_assert(sizeof(kModels) / sizeof(kModels[0]) == kNumVariants, "one model entry per variant");
 
 // Level 0 of a wavefront-check variant runs the plain kernel of its tile.
 template <int BM, int BN, int BK, int WM, int WN, bool WAVE = false>
@@ -85,6 +91,7 @@ hipError_t launch_shape_retry(const LaunchArgs& a, int grid, hipStream_t s) {
 }  // namespace
 
 int fp32_variant_count() { return kNumVariants; }
+VariantModel fp32_variant_model(int idx) { return kModels[idx]; }
 Variant fp32_variant(int idx) { return kVariants[idx]; }
 int fp32_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
     for (int v = 0; v < kNumVariants; ++v) {

@@ -62,6 +62,15 @@ struct Variant {
 // Kernel variants compiled for FP32 operands, in preference order.
 int fp32_variant_count();
 Variant fp32_variant(int idx);
+// Default-selection cost model of an FP32 variant: workgroups resident per
+// compute unit, wavefronts per workgroup, and the throughput (TFLOP/s) of its
+// plain and online FT kernels with every compute unit full (measured on
+// MI355X at 8192^3).
+struct VariantModel {
+    int wg_per_cu, waves_per_wg;
+    float tflops_plain, tflops_ft;
+};
+VariantModel fp32_variant_model(int idx);
 int fp32_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 
 // Launch the FP32 kernel variant `idx` (A, B as float).  `inject` selects the instantiation

@@ -132,19 +132,25 @@ def test_nonfused_and_batched_with_null_handle_are_invalid():
     assert st == F.INVALID and rep.report.bad_arg == 1
 
 
-def test_select_config_fills_the_gpu_and_checks_every_256_k():
+def test_select_config_follows_the_measured_best_tile_and_checks_every_256_k():
+    """Automatic selection (a modelled time per FP32 tile: waves of resident
+    workgroups at each tile's measured full-load rate) picks, for online FT at
+    these square sizes, the tile that was fastest when every compute-tile
+    variant was timed on MI355X; compute-tile checks, a check every 256 k."""
+    measured_best = {1024: 128, 2048: 128, 2560: 128, 3072: 128, 3584: 256, 4096: 256, 5120: 128, 6144: 128,
+                     8192: 256}
+    for N, t in measured_best.items():
+        c = F.ftgemm_select_config(F.F32, N, N, N, F.FT_CORRECT)
+        assert (c.m_tile, c.n_tile) == (t, t), (N, c.as_tuple())
     for (m, n) in [(8192, 8192), (4096, 4096), (2048, 2048), (65536, 256), (256, 65536), (3001, 1999),
-                   (100, 100)]:
-        c = F.ftgemm_select_config(F.F32, m, n, 1024)
-        tiles = -(-m // c.m_tile) * -(-n // c.n_tile)
-        assert c.k_step * c.check_interval == 256
-        assert tiles >= 256 or (c.m_tile, c.n_tile) == (64, 64), (m, n, c.as_tuple())
-        assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)    # automatic selection: compute-tile checks
+                   (100, 100), (1, 1)]:
+        for level in (F.FT_OFF, F.FT_DETECT, F.FT_CORRECT, F.FT_CORRECT | F.FT_RECOMPUTE):
+            c = F.ftgemm_select_config(F.F32, m, n, 1024, level)
+            assert c.k_step * c.check_interval == 256
+            assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)    # automatic selection: compute-tile checks
     for dtype in (F.BF16, F.F8E4M3):
         c = F.ftgemm_select_config(dtype, 8192, 8192, 8192)
         assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)
-    assert F.ftgemm_select_config(F.F32, 8192, 8192, 8192).as_tuple()[:2] == (256, 256)
-    assert F.ftgemm_select_config(F.F32, 2048, 2048, 2048).as_tuple()[:2] == (128, 128)
 
 
 def test_status_strings():
