@@ -434,7 +434,10 @@ def bench_irregular(args):
         flop = 2.0 * m * n * k
         g = W.rng(3, W.STREAM_SITES)
         counts, _ = W.rate_schedule(g, 100, ms_tuned * 1e-3, 4)
-        inj = dict(injected=0, corrected=0, events=0)
+        # above_threshold: applied faults whose logged residual at the first
+        # check after them exceeds its threshold (the others are below what
+        # the check can see: benign by construction)
+        inj = dict(injected=0, above_threshold=0, corrected=0, events=0)
         for c_l in counts:
             sites = W.fault_sites(g, m, n, k, cfg[0], cfg[1], cfg[2], cfg[3], int(c_l), kind=W.KIND_XOR,
                                   bits=range(23, 31))
@@ -442,7 +445,10 @@ def bench_irregular(args):
             rep = F.ReportBuffer(1024)
             F.ftgemm_run(h, m, n, k, 1.0, A.data_ptr(), m, B.data_ptr(), k, 0.0, C.data_ptr(), m, F.FT_CORRECT,
                          0.0, stream.cuda_stream, rep)
+            flog = F.ftgemm_get_injection_log(h) if len(sites) else []
             inj["injected"] += len(sites)
+            inj["above_threshold"] += sum(1 for f in flog if not (abs(f["r_row"]) <= f["tau_row"] and
+                                                                   abs(f["r_col"]) <= f["tau_col"]))
             inj["corrected"] += int(rep.report.corrected)
             inj["events"] += int(rep.report.n_events)
         F.ftgemm_set_injection(h, None)
