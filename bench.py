@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2516.6
+PEAK_FP64_TFLOPS = 78.6      # FP64 vector FMA and FP64 matrix cores alike on MI355X
 METRIC = "FT-GEMM TFLOP/s & %MFMA peak vs plain GEMM (same GPU), overhead %, detect/correct rate"
 
 
@@ -50,9 +51,10 @@ def parse():
                         "problems in one persistent launch vs a loop of launches; irregular: tall-skinny, "
                         "small-K and odd shapes, autotuned vs fixed configuration; ablation: fused online "
                         "ABFT against the same checks run as separate launches (FP32 8192^3, beta = 0)")
-    p.add_argument("--dtype", choices=("f32", "bf16"), default="f32",
+    p.add_argument("--dtype", choices=("f32", "bf16", "f64"), default="f32",
                    help="f32: the FP32 square workload (beta = 1); bf16: A, B heavy-tailed N(0,1) "
-                        "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel)")
+                        "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel); f64: the binary64 "
+                        "path (ftgemm_run_f64), N(0,1) operands, beta = 1")
     p.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     p.add_argument("--skip-injection", action="store_true", help="do not run the injection-rate sweep")
     p.add_argument("--plain-only", action="store_true", help="time only the FT-off kernel (profiling)")
@@ -130,6 +132,8 @@ def main():
         return bench_irregular(args)
     if args.workload == "ablation":
         return bench_ablation(args)
+    if args.dtype == "f64":
+        return bench_f64(args)
     N = args.size
     m = n = k = N
     bf16 = args.dtype == "bf16"
@@ -302,6 +306,66 @@ def _line(metric_value, ms, unit, dtype, config, extra, args, higher=True):
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def bench_f64(args):
+    """The binary64 path at size^3 (default 8192^3): N(0,1) A, B, C in HBM,
+    alpha = 1, beta = 1; online FT (a check every 256 k), detect-only and
+    plain launches timed with HIP events on the launch stream; one +1e3 fault
+    per tile at a seeded k-step, row and column in a separate run, all of
+    which must be corrected.  The kernel is SIMT FP64 FMA (no matrix cores),
+    so the roofline is the FP64 FMA rate."""
+    import torch
+
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    N = args.size
+    m = n = k = N
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2305_01024 + 64)
+    dA = torch.randn(k, m, device="cuda", dtype=torch.float64, generator=gen)
+    dB = torch.randn(n, k, device="cuda", dtype=torch.float64, generator=gen)
+    dC = torch.randn(n, m, device="cuda", dtype=torch.float64, generator=gen)
+    h = F.ftgemm_create(F.F64, 0)
+
+    def call(level=F.FT_CORRECT, report=None):
+        return F.ftgemm_run_f64(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, 1.0, dC.data_ptr(), m, level,
+                                0.0, stream.cuda_stream, report)
+    rep = F.ReportBuffer(16)
+    assert call(report=rep) == F.OK and rep.report.n_events == 0
+    cfg = rep.report.config.as_tuple()
+    ms_ft = timed(call, args.steps, args.warmup, stream)
+    ms_det = timed(lambda: call(F.FT_DETECT), args.steps, args.warmup, stream)
+    ms_plain = timed(lambda: call(F.FT_OFF), args.steps, args.warmup, stream)
+    flop = 2.0 * m * n * k
+    tf = flop / (ms_ft * 1e-3) / 1e12
+    ntm, ntn, nk = -(-m // cfg[0]), -(-n // cfg[1]), -(-k // cfg[2])
+    g = W.rng(64, W.STREAM_SITES)
+    sites = np.zeros(ntm * ntn, dtype=F.FAULT_DTYPE)
+    for q in range(ntm * ntn):
+        sites[q] = (q // ntn, q % ntn, int(g.integers(0, nk)), int(g.integers(0, min(cfg[0], m - (q // ntn) * cfg[0]))),
+                    int(g.integers(0, min(cfg[1], n - (q % ntn) * cfg[1]))), W.KIND_ADD, 1e3, 0)
+    F.ftgemm_set_injection(h, sites)
+    rep = F.ReportBuffer(len(sites) + 16)
+    st = call(report=rep)
+    F.ftgemm_set_injection(h, None)
+    inj = {"injected": len(sites), "corrected": int(rep.report.corrected),
+           "uncorrectable": int(rep.report.uncorrectable), "status": int(st)}
+    F.ftgemm_destroy(h)
+    out = {"ft_tflops": round(tf, 3), "plain_tflops": round(flop / ms_plain / 1e9, 3),
+           "detect_only_tflops": round(flop / ms_det / 1e9, 3),
+           "ft_overhead_pct": round(100 * (ms_ft / ms_plain - 1), 2),
+           "detect_only_overhead_pct": round(100 * (ms_det / ms_plain - 1), 2),
+           "injection_one_per_tile": inj,
+           "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None},
+           "cpu_baseline": None}
+    log(f"f64: {out}")
+    _line(tf, ms_ft, "TFLOP/s", "f64",
+          {"workload": f"fp64 square FT-GEMM M=N=K={N}, A,B,C~N(0,1), alpha=1, beta=1, online detect+correct",
+           "m": m, "n": n, "k": k, "tile": list(cfg[:2]), "k_step": cfg[2], "check_interval": cfg[3]}, out, args)
 
 
 def bench_batched(args):

@@ -49,7 +49,7 @@ extern "C" {
 
 typedef struct ftgemm_ctx* ftgemm_t;
 
-enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2 };
+enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2, FTGEMM_F64 = 3 };
 
 /* ft_level: 0 = plain GEMM (fault tolerance compiled out of the kernel);
  * 1 = detect only, one check of the accumulated tile at the end of the
@@ -214,6 +214,23 @@ int ftgemm_run_nonfused(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float 
                         const void* A, int64_t lda, const void* B, int64_t ldb, float beta,
                         float* C, int64_t ldc, int check_k, float tol, hipStream_t stream,
                         ftgemm_report_t* report);
+
+/* C = alpha * A * B + beta * C in binary64 for a handle created with
+ * FTGEMM_F64 (ftgemm_run refuses such a handle: its C is float).  A, B, C
+ * are double, column-major, device pointers as in ftgemm_run; products,
+ * accumulation, encodings, reference checksums and the check are binary64,
+ * and the threshold takes u = 2^-53 (section 6 names further data types,
+ * double-precision complex among them, as future work).  One compiled configuration: 128 x 128 tiles,
+ * k-step 16, a check every 16 k-steps (256 k) unless a configuration is
+ * forced; ft_level 0, 1 or 2 (FTGEMM_FT_RECOMPUTE is not supported:
+ * FTGEMM_UNSUPPORTED).  tol <= 0 selects c = 2.  Events and the fault log
+ * carry their values rounded to float.  Injected FTGEMM_FAULT_XOR sites flip
+ * bit (int)payload of the 64-bit value (0..63).  Same return codes, report
+ * and bad_arg positions as ftgemm_run. */
+int ftgemm_run_f64(ftgemm_t handle, int64_t m, int64_t n, int64_t k, double alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                   double* C, int64_t ldc, int ft_level, double tol, hipStream_t stream,
+                   ftgemm_report_t* report);
 
 /* One problem of a batched call: C = alpha * (scale_a A) (scale_b B) +
  * beta * C, column-major as in ftgemm_run, with its own dtype (FTGEMM_F32 or

@@ -29,6 +29,7 @@ EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED = 
 CLS_BENIGN, CLS_GREY, CLS_MUST = 0, 1, 2
 
 U_FP32 = 2.0 ** -24   # unit roundoff of IEEE binary32 (round to nearest)
+U_FP64 = 2.0 ** -53   # unit roundoff of IEEE binary64 (round to nearest)
 
 
 def build(extra_flags=(), out=None) -> str:

@@ -80,10 +80,11 @@ bool wants_recompute(int ft_level) { return (ft_level & FTGEMM_FT_RECOMPUTE) != 
 
 int variant_count(int dtype) {
     return dtype == FTGEMM_BF16 ? bf16_variant_count() : dtype == FTGEMM_F8E4M3 ? fp8_variant_count()
-                                                                               : fp32_variant_count();
+                           : dtype == FTGEMM_F64 ? fp64_variant_count() : fp32_variant_count();
 }
 Variant variant_at(int dtype, int v) {
-    return dtype == FTGEMM_BF16 ? bf16_variant(v) : dtype == FTGEMM_F8E4M3 ? fp8_variant(v) : fp32_variant(v);
+    return dtype == FTGEMM_BF16 ? bf16_variant(v) : dtype == FTGEMM_F8E4M3 ? fp8_variant(v)
+                           : dtype == FTGEMM_F64 ? fp64_variant(v) : fp32_variant(v);
 }
 // A check shape of 0 stands for the compute tile's.
 ftgemm_config_t normalized(ftgemm_config_t c) {
@@ -95,11 +96,12 @@ int find_variant(int dtype, const ftgemm_config_t& c0) {
     const ftgemm_config_t c = normalized(c0);
     return dtype == FTGEMM_BF16     ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
            : dtype == FTGEMM_F8E4M3 ? fp8_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
+           : dtype == FTGEMM_F64    ? fp64_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
                                     : fp32_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n);
 }
 bool compute_tile_check(const Variant& x) { return x.check_m == x.m_tile && x.check_n == x.n_tile; }
 bool dtype_supported(int dtype) {
-    return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3;
+    return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3 || dtype == FTGEMM_F64;
 }
 
 // Modelled time of an FP32 variant on an m x n output (the k extent is common
@@ -433,7 +435,8 @@ int ftgemm_set_injection(ftgemm_t h, const ftgemm_fault_t* faults, int n) {
         if (f.tile_m < 0 || f.tile_n < 0 || f.kstep < 0 || f.row < 0 || f.col < 0 || f.problem < 0)
             return FTGEMM_INVALID;
         if (f.kind != FTGEMM_FAULT_ADD && f.kind != FTGEMM_FAULT_XOR) return FTGEMM_INVALID;
-        if (f.kind == FTGEMM_FAULT_XOR && !(f.payload >= 0.f && f.payload <= 31.f)) return FTGEMM_INVALID;
+        const float top_bit = h->dtype == FTGEMM_F64 ? 63.f : 31.f;
+        if (f.kind == FTGEMM_FAULT_XOR && !(f.payload >= 0.f && f.payload <= top_bit)) return FTGEMM_INVALID;
     }
     DeviceGuard g(h->device);
     if (n > h->fault_cap) {
@@ -485,7 +488,7 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
         if (report) report->bad_arg = bad;
         return FTGEMM_INVALID;
     }
-    if (!dtype_supported(h->dtype)) return FTGEMM_UNSUPPORTED;
+    if (!dtype_supported(h->dtype) || h->dtype == FTGEMM_F64) return FTGEMM_UNSUPPORTED;   // FP64: ftgemm_run_f64
     const float c = tol > 0.f ? tol : 2.0f;
     if (report) report->tol_used = c;
     if (m == 0 || n == 0) return FTGEMM_OK;
@@ -568,6 +571,87 @@ int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const v
     // check tiles that hold part of C (a wavefront tile past the edge is not checked)
     const int64_t nchk = ((m + cfg.check_m - 1) / cfg.check_m) * ((n + cfg.check_n - 1) / cfg.check_n);
     return fill_report(h, stream, report, (uint64_t)(nchk * per_tile), recompute);
+}
+
+int ftgemm_run_f64(ftgemm_t h, int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int ft_level, double tol,
+                   hipStream_t stream, ftgemm_report_t* report) {
+    int32_t bad = 0;
+    if (report) {
+        report->checks = report->detected = report->corrected = 0;
+        report->uncorrectable = report->checksum_only = 0;
+        report->n_events = 0;
+        report->bad_arg = 0;
+        report->tol_used = 0.f;
+        report->bad_problem = -1;
+        report->recomputed = report->recompute_failed = 0;
+        std::memset(&report->config, 0, sizeof(report->config));
+    }
+    if (!h) {
+        if (report) report->bad_arg = 1;
+        return FTGEMM_INVALID;
+    }
+    if (ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level, (float)std::min(tol, 1e31), &bad) != FTGEMM_OK) {
+        if (report) report->bad_arg = bad;
+        return FTGEMM_INVALID;
+    }
+    if (h->dtype != FTGEMM_F64 || wants_recompute(ft_level)) return FTGEMM_UNSUPPORTED;
+    const float c = tol > 0.0 ? (float)tol : 2.0f;
+    if (report) report->tol_used = c;
+    if (m == 0 || n == 0) return FTGEMM_OK;
+    if (!C) {
+        if (report) report->bad_arg = 11;
+        return FTGEMM_INVALID;
+    }
+    DeviceGuard g(h->device);
+    if (k == 0 || alpha == 0.0) {
+        FT_HIP(launch_scale64(C, ldc, (int32_t)m, (int32_t)n, beta, stream));
+        if (report) FT_HIP(hipStreamSynchronize(stream));
+        return FTGEMM_OK;
+    }
+    if (!A || !B) {
+        if (report) report->bad_arg = !A ? 6 : 8;
+        return FTGEMM_INVALID;
+    }
+    ftgemm_config_t cfg;
+    if (h->forced) cfg = h->cfg;
+    else select_variant(FTGEMM_F64, m, n, ft_level, &cfg);
+    const int variant = find_variant(FTGEMM_F64, cfg);
+    if (variant < 0) return FTGEMM_UNSUPPORTED;
+
+    const bool inject = h->n_faults > 0;
+    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
+    F64Args a{};
+    a.A = A;
+    a.B = B;
+    a.C = C;
+    a.lda = lda;
+    a.ldb = ldb;
+    a.ldc = ldc;
+    a.M = (int32_t)m;
+    a.N = (int32_t)n;
+    a.K = (int32_t)k;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.tol_c = c;
+    a.check_interval = ft_level == 1 ? INT32_MAX : cfg.check_interval;   // detect-only: after the last step
+    a.ft_level = ft_level;
+    a.problem = 0;
+    a.events = h->d_events;
+    a.counters = h->d_counters;
+    a.event_cap = h->event_cap;
+    a.faults = inject ? h->d_faults : nullptr;
+    a.n_faults = inject ? h->n_faults : 0;
+    a.fault_log = h->d_flog;
+    a.fault_log_cap = h->flog_cap;
+    FT_HIP(launch_fp64(variant, inject, a, stream));
+    if (!report) return FTGEMM_OK;
+    report->config = cfg;
+    const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
+    const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
+                           : ft_level == 1 ? 1 : 0;
+    const int64_t nchk = ((m + cfg.check_m - 1) / cfg.check_m) * ((n + cfg.check_n - 1) / cfg.check_n);
+    return fill_report(h, stream, report, (uint64_t)(nchk * per_tile));
 }
 
 int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
@@ -793,7 +877,7 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
                               ft_level, 0.f, nullptr) != FTGEMM_OK || m == 0 || n == 0 || k == 0 ||
         max_k_between_checks < 0)
         return FTGEMM_INVALID;
-    if (!dtype_supported(h->dtype)) return FTGEMM_UNSUPPORTED;
+    if (!dtype_supported(h->dtype) || h->dtype == FTGEMM_F64) return FTGEMM_UNSUPPORTED;
     ft_level = base_level(ft_level);   // configurations are kept per level; recompute does not change them
     const int kmax = max_k_between_checks > 0 ? max_k_between_checks : 256;
     const size_t esz = h->dtype == FTGEMM_F32 ? 4 : h->dtype == FTGEMM_BF16 ? 2 : 1;

@@ -1,0 +1,468 @@
+// ftgemm_fp64.hip -- FP64 online ABFT GEMM for gfx950 (MI355X).
+//
+// C = alpha * A * B + beta * C in binary64, A, B, C column-major.  On MI355X
+// the FP64 vector FMA rate equals the FP64 matrix-core rate, so this kernel
+// keeps the paper's own outer-product SIMT form (section 3, 8 x 8 thread
+// tiles): a workgroup of 256 threads computes a 128 x 128 tile, each thread an 8 x 8 micro-tile
+// (rows 8 ty .. 8 ty + 7, columns 8 tx .. 8 tx + 7, tid = 16 ty + tx) with
+// v_fma_f64, k-steps of 16 staged through double-buffered LDS.
+//
+// Fault tolerance, threadblock-level (section 4.2.3), online (section 2.2,
+// Eq. 4), all in FP64:
+//   * encodings of each staged panel (Eq. 1-2) from the staging registers:
+//       w[k] = sum_i A[i,k]: every wave holds one whole column of the A panel
+//       per load slot, reduced across the wave;
+//       v[k] = sum_j B[k,j]: per wave partial sums, added when read;
+//   * reference checksums (Eq. 3-4): threads 0..127 own rows (R_i, ||a_i||^2),
+//     threads 128..255 own columns (S_j, ||b_j||^2);
+//   * a check every `check_interval` k-steps and after the last: row and
+//     column sums of the micro-tiles (lane shuffles in a wave, LDS across
+//     waves), residuals against R and S, the threshold with u = 2^-53;
+//     one flagged row and one flagged column: the element at their
+//     intersection is rebuilt from the row checksum (section 4.2.1, 5.3);
+//     other patterns are logged and the flagged checksums re-based.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ftgemm_internal.h"
+
+namespace ftgemm_impl {
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16, NT = 256, TPT = 8;   // tile, k-step, threads, micro-tile
+constexpr int LP = BM + 2;            // LDS row pitch in doubles (16-byte aligned rows, staggered banks)
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53, unit roundoff of binary64
+constexpr int kMaxF64Faults = 32;
+
+struct F64Lds {
+    double As[2][BK][LP];         // A panel, k-major (i contiguous)
+    double Bs[2][BK][LP];         // B panel, k-major (j contiguous)
+    double wsum[2][BK];           // e^T A of the panel
+    double vpart[2][4][BK];       // B e of the panel, per wave
+    double rowsum[BM];            // row sums of the tile
+    double colpart[4][BN];        // column sums per wave (each wave holds 4 row groups)
+    double nsum[4];               // per-wave sums of ||a_i|| (waves 0, 1) and ||b_j|| (waves 2, 3)
+    int census[4][4];             // per wave: #rows, first row, #cols, first col flagged
+    double bc[5];                 // first flagged row: R, r, tau; first flagged column: r, tau
+    ftgemm_fault_t fault[kMaxF64Faults];
+    int fslot[kMaxF64Faults];
+    int nf;
+};
+
+__device__ __forceinline__ double wave_sum64(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double flip64(double v, int bit) {
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)(1ull << (bit & 63)));
+}
+
+// One 128 x 128 tile (tm, tn).  FT: 0 plain, 1 detect-only, 2 online.
+template <int FT, bool INJ>
+__device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int i0 = tm * BM, j0 = tn * BN;
+    const int mI = min(BM, a.M - i0), nJ = min(BN, a.N - j0);
+    const int nk = (a.K + BK - 1) / BK;
+    const bool row_owner = tid < BM;
+    const int own = row_owner ? tid : tid - BM;   // owned tile row or column
+
+    double acc[TPT][TPT];
+#pragma unroll
+    for (int r = 0; r < TPT; ++r)
+#pragma unroll
+        for (int c = 0; c < TPT; ++c) acc[r][c] = 0.0;
+    double ref = 0.0, nrm2 = 0.0;   // R_i or S_j, ||a_i||^2 or ||b_j||^2 over the k prefix
+
+    int fnext = 0, flogged = 0;
+    if constexpr (INJ) {
+        if (tid == 0) s.nf = 0;
+        __syncthreads();
+        for (int q = tid; q < a.n_faults; q += NT) {
+            const ftgemm_fault_t f = a.faults[q];
+            if (f.problem == a.problem && f.tile_m == tm && f.tile_n == tn && f.row < BM && f.col < BN) {
+                const int x = atomicAdd(&s.nf, 1);
+                if (x < kMaxF64Faults) { s.fault[x] = f; s.fslot[x] = -1; }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {   // order by k-step
+            const int n = min(s.nf, kMaxF64Faults);
+            s.nf = n;
+            for (int x = 1; x < n; ++x) {
+                const ftgemm_fault_t f = s.fault[x];
+                int y = x - 1;
+                while (y >= 0 && s.fault[y].kstep > f.kstep) { s.fault[y + 1] = s.fault[y]; --y; }
+                s.fault[y + 1] = f;
+            }
+        }
+    }
+
+    // ---- staging: each thread holds 4 pairs of A (rows 2p, 2p+1 of column k = 4 r + wave)
+    // and 4 pairs of B (k = 2 (tid % 8), +1 of column j = tid / 8 + 32 r) ----
+    double ra[4][2], rb[4][2];
+    auto load = [&](int t) {
+        const int k0 = t * BK;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * r + wave, i = 2 * lane;
+            const int gk = k0 + k;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool in = gk < a.K && i + e < mI;
+                const double* p = in ? a.A + (size_t)gk * a.lda + (i0 + i + e) : a.A;
+                const double x = *p;
+                ra[r][e] = in ? x : 0.0;
+            }
+            const int j = tid / 8 + 32 * r, kk = 2 * (tid % 8);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool in = k0 + kk + e < a.K && j < nJ;
+                const double* p = in ? a.B + (size_t)(j0 + j) * a.ldb + (k0 + kk + e) : a.B;
+                const double x = *p;
+                rb[r][e] = in ? x : 0.0;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * r + wave, i = 2 * lane;
+            s.As[buf][k][i] = ra[r][0];
+            s.As[buf][k][i + 1] = ra[r][1];
+            const int j = tid / 8 + 32 * r, kk = 2 * (tid % 8);
+            s.Bs[buf][kk][j] = rb[r][0];
+            s.Bs[buf][kk + 1][j] = rb[r][1];
+        }
+        if constexpr (FT > 0) {
+            // e^T A: wave `wave` holds all 128 rows of column 4 r + wave
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double w = wave_sum64(ra[r][0] + ra[r][1]);
+                if (lane == 0) s.wsum[buf][4 * r + wave] = w;
+            }
+            // B e: the thread's 4 columns of its k pair, then the 8 lanes of
+            // the wave with the same k pair (lane bits 3..5)
+            double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { v0 += rb[r][0]; v1 += rb[r][1]; }
+#pragma unroll
+            for (int off = 8; off <= 32; off <<= 1) {
+                v0 += __shfl_xor(v0, off, 64);
+                v1 += __shfl_xor(v1, off, 64);
+            }
+            if (lane < 8) {
+                s.vpart[buf][wave][2 * lane] = v0;
+                s.vpart[buf][wave][2 * lane + 1] = v1;
+            }
+        }
+    };
+
+    // ---- online check after k-step t (kp = k indices accumulated) ----
+    auto check = [&](int t, int kp) {
+        // row sums (over the 16 threads tx of a row group: lane bits 0..3)
+        double rs[TPT], cs[TPT];
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            double x = 0.0;
+#pragma unroll
+            for (int c = 0; c < TPT; ++c) x += acc[r][c];
+            rs[r] = x;
+        }
+#pragma unroll
+        for (int c = 0; c < TPT; ++c) {
+            double x = 0.0;
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) x += acc[r][c];
+            cs[c] = x;
+        }
+#pragma unroll
+        for (int r = 0; r < TPT; ++r)
+#pragma unroll
+            for (int off = 1; off <= 8; off <<= 1) rs[r] += __shfl_xor(rs[r], off, 64);
+#pragma unroll
+        for (int c = 0; c < TPT; ++c)
+#pragma unroll
+            for (int off = 16; off <= 32; off <<= 1) cs[c] += __shfl_xor(cs[c], off, 64);
+        if (tx == 0) {
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) s.rowsum[TPT * ty + r] = rs[r];
+        }
+        if ((lane >> 4) == 0) {
+#pragma unroll
+            for (int c = 0; c < TPT; ++c) s.colpart[wave][TPT * tx + c] = cs[c];
+        }
+        const double nv = sqrt(nrm2);
+        const double ws = wave_sum64(nv);
+        if (lane == 0) s.nsum[wave] = ws;
+        __syncthreads();
+
+        const double sa = s.nsum[0] + s.nsum[1], sb = s.nsum[2] + s.nsum[3];
+        const double base = (double)a.tol_c * 2.0 * kU64;
+        double res = 0.0, tau = 0.0;
+        bool flag = false;
+        if (row_owner && own < mI) {
+            res = s.rowsum[own] - ref;
+            tau = base * (double)(kp + nJ + 1) * nv * sb;
+            flag = !(fabs(res) <= tau);
+        } else if (!row_owner && own < nJ) {
+            res = (s.colpart[0][own] + s.colpart[1][own]) + (s.colpart[2][own] + s.colpart[3][own]) - ref;
+            tau = base * (double)(kp + mI + 1) * nv * sa;
+            flag = !(fabs(res) <= tau);
+        }
+        // owners are in index order within a wave: the first flagged line is
+        // the lowest flagged lane's
+        const unsigned long long b = __ballot(flag);
+        if (lane == 0) {
+            const int first = b ? (tid + (int)__builtin_ctzll(b)) - (row_owner ? 0 : BM) : -1;
+            s.census[wave][0] = row_owner ? __popcll(b) : 0;
+            s.census[wave][1] = row_owner ? first : -1;
+            s.census[wave][2] = row_owner ? 0 : __popcll(b);
+            s.census[wave][3] = row_owner ? -1 : first;
+        }
+        if constexpr (INJ) {   // complete the log entries this check is the first to see
+            for (int q = flogged; q < fnext; ++q) {
+                const int slot = s.fslot[q];
+                if (slot < 0 || slot >= a.fault_log_cap) continue;
+                if (row_owner && own == s.fault[q].row) {
+                    a.fault_log[slot].r_row = (float)res; a.fault_log[slot].tau_row = (float)tau;
+                }
+                if (!row_owner && own == s.fault[q].col) {
+                    a.fault_log[slot].r_col = (float)res; a.fault_log[slot].tau_col = (float)tau;
+                }
+                if (tid == 0) a.fault_log[slot].check_step = t;
+            }
+            flogged = fnext;
+        }
+        __syncthreads();
+        int nr = 0, ncl = 0, fr = -1, fc = -1;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            nr += s.census[w][0];
+            ncl += s.census[w][2];
+            if (s.census[w][1] >= 0 && (fr < 0 || s.census[w][1] < fr)) fr = s.census[w][1];
+            if (s.census[w][3] >= 0 && (fc < 0 || s.census[w][3] < fc)) fc = s.census[w][3];
+        }
+        if (nr + ncl == 0) return;
+
+        // rare path (uniform branch)
+        const bool online = (FT == 2) || a.ft_level == 2;
+        const bool correct = online && nr == 1 && ncl == 1;
+        if (row_owner && own == fr) { s.bc[0] = ref; s.bc[1] = res; s.bc[2] = tau; }
+        if (!row_owner && own == fc) { s.bc[3] = res; s.bc[4] = tau; }
+        __syncthreads();
+        if (correct) {
+            // P_ij = R_i - sum_{j' != j} P_ij': the 16 threads of row group fr / 8
+            const int fry = fr / TPT, frr = fr % TPT, fcx = fc / TPT, fcc = fc % TPT;
+            double part = 0.0, oldv = 0.0;
+            const bool mine_row = ty == fry;
+#pragma unroll
+            for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                for (int c = 0; c < TPT; ++c) {
+                    const bool in_row = mine_row && r == frr;
+                    const bool hit = in_row && tx == fcx && c == fcc;
+                    part += (in_row && !hit) ? acc[r][c] : 0.0;
+                    oldv = hit ? acc[r][c] : oldv;
+                }
+#pragma unroll
+            for (int off = 1; off <= 8; off <<= 1) part += __shfl_xor(part, off, 64);
+            const double newv = s.bc[0] - part;
+            const bool owner = mine_row && tx == fcx;
+#pragma unroll
+            for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                for (int c = 0; c < TPT; ++c) acc[r][c] = (owner && r == frr && c == fcc) ? newv : acc[r][c];
+            if (owner) {
+                const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+                atomicAdd(&a.counters[CNT_DETECTED], 1u);
+                atomicAdd(&a.counters[CNT_CORRECTED], 1u);
+                if ((int)e < a.event_cap) {
+                    ftgemm_event_t E;
+                    E.problem = a.problem; E.tile_m = tm; E.tile_n = tn; E.kstep = t; E.row = fr; E.col = fc;
+                    E.kind = FTGEMM_EV_CORRECTED; E.n_rows = 1; E.n_cols = 1; E.pad_ = 0;
+                    E.value_before = (float)oldv; E.value_after = (float)newv;
+                    E.r_row = (float)s.bc[1]; E.tau_row = (float)s.bc[2];
+                    E.r_col = (float)s.bc[3]; E.tau_col = (float)s.bc[4];
+                    a.events[e] = E;
+                }
+            }
+        } else {
+            const int kind = !online ? FTGEMM_EV_DETECTED
+                           : (nr == 1 && ncl == 0) ? FTGEMM_EV_CHECKSUM_ROW
+                           : (nr == 0 && ncl == 1) ? FTGEMM_EV_CHECKSUM_COL
+                           : FTGEMM_EV_UNCORRECTABLE;
+            if (online && flag) ref += res;   // re-base on the accumulator
+            if (tid == 0) {
+                const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+                atomicAdd(&a.counters[CNT_DETECTED], 1u);
+                if (kind == FTGEMM_EV_UNCORRECTABLE) atomicAdd(&a.counters[CNT_UNCORRECTABLE], 1u);
+                if (kind == FTGEMM_EV_CHECKSUM_ROW || kind == FTGEMM_EV_CHECKSUM_COL)
+                    atomicAdd(&a.counters[CNT_CHECKSUM_ONLY], 1u);
+                if ((int)e < a.event_cap) {
+                    ftgemm_event_t E;
+                    E.problem = a.problem; E.tile_m = tm; E.tile_n = tn; E.kstep = t; E.row = fr; E.col = fc;
+                    E.kind = kind; E.n_rows = nr; E.n_cols = ncl; E.pad_ = 0;
+                    E.value_before = E.value_after = 0.f;
+                    E.r_row = fr >= 0 ? (float)s.bc[1] : 0.f; E.tau_row = fr >= 0 ? (float)s.bc[2] : 0.f;
+                    E.r_col = fc >= 0 ? (float)s.bc[3] : 0.f; E.tau_col = fc >= 0 ? (float)s.bc[4] : 0.f;
+                    a.events[e] = E;
+                }
+            }
+        }
+        __syncthreads();   // s.bc is rewritten by the next check
+    };
+
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) load(t + 1);
+        // the product of this k-step, one k at a time (outer products)
+#pragma unroll 4
+        for (int k = 0; k < BK; ++k) {
+            double av[TPT], bv[TPT];
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) av[r] = s.As[cur][k][TPT * ty + r];
+#pragma unroll
+            for (int c = 0; c < TPT; ++c) bv[c] = s.Bs[cur][k][TPT * tx + c];
+#pragma unroll
+            for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                for (int c = 0; c < TPT; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+        }
+        if constexpr (FT > 0) {
+            // reference checksums (Eq. 4): R_i += sum_k A[i,k] (B e)[k], S_j += sum_k (e^T A)[k] B[k,j]
+#pragma unroll
+            for (int k = 0; k < BK; ++k) {
+                const double x = row_owner ? s.As[cur][k][own] : s.Bs[cur][k][own];
+                const double y = row_owner ? (s.vpart[cur][0][k] + s.vpart[cur][1][k]) +
+                                                 (s.vpart[cur][2][k] + s.vpart[cur][3][k])
+                                           : s.wsum[cur][k];
+                ref = fma(x, y, ref);
+                nrm2 = fma(x, x, nrm2);
+            }
+        }
+        if (t + 1 < nk) store(cur ^ 1);
+        if constexpr (INJ) {   // faults of k-step t hit the accumulator after its update
+            while (fnext < s.nf && s.fault[fnext].kstep == t) {
+                const ftgemm_fault_t f = s.fault[fnext];
+                const bool owner = f.row / TPT == ty && f.col / TPT == tx;
+                const int fr = f.row % TPT, fc = f.col % TPT;
+                double oldv = 0.0, newv = 0.0;
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                    for (int c = 0; c < TPT; ++c) {
+                        const bool hit = owner && r == fr && c == fc;
+                        const double x = acc[r][c];
+                        const double y = f.kind == FTGEMM_FAULT_XOR ? flip64(x, (int)f.payload) : x + (double)f.payload;
+                        oldv = hit ? x : oldv;
+                        newv = hit ? y : newv;
+                        acc[r][c] = hit ? y : x;
+                    }
+                if (owner) {
+                    const int slot = (int)atomicAdd(&a.counters[CNT_FAULTS], 1u);
+                    s.fslot[fnext] = slot;
+                    if (slot < a.fault_log_cap) {
+                        ftgemm_fault_log_t L;
+                        L.problem = a.problem; L.tile_m = tm; L.tile_n = tn; L.kstep = t;
+                        L.row = f.row; L.col = f.col; L.kind = f.kind; L.check_step = -1;
+                        L.old_v = (float)oldv; L.new_v = (float)newv;
+                        L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
+                        L.pad0_ = L.pad1_ = 0.f;
+                        a.fault_log[slot] = L;
+                    }
+                }
+                ++fnext;
+            }
+            __syncthreads();   // s.fslot written by the owner, read by the check
+        }
+        if constexpr (FT > 0) {
+            if (((t + 1) % a.check_interval == 0) || t == nk - 1) check(t, min((t + 1) * BK, a.K));
+        }
+        __syncthreads();
+    }
+
+    // epilogue: C = alpha P + beta C (beta == 0: C is not read)
+#pragma unroll
+    for (int c = 0; c < TPT; ++c) {
+        const int j = TPT * tx + c;
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const int i = TPT * ty + r;
+            if (i < mI && j < nJ) {
+                double* pc = a.C + (size_t)(j0 + j) * a.ldc + (i0 + i);
+                double v = a.alpha * acc[r][c];
+                if (a.beta != 0.0) v = fma(a.beta, *pc, v);
+                *pc = v;
+            }
+        }
+    }
+}
+
+template <int FT, bool INJ>
+__global__ __launch_bounds__(NT, 2) void ftgemm_f64_kernel(F64Args a) {
+    __shared__ F64Lds s;
+    const int ntm = (a.M + BM - 1) / BM;
+    tile64<FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, s);
+}
+
+__global__ void scale64_kernel(double* C, int64_t ldc, int32_t M, int32_t N, double beta) {
+    const int64_t total = (int64_t)M * N;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = x / M, i = x % M;
+        double* p = C + j * ldc + i;
+        *p = (beta == 0.0) ? 0.0 : beta * *p;
+    }
+}
+
+constexpr Variant kVariantsF64[] = {
+    {BM, BN, BK, BM, BN},
+};
+
+}  // namespace
+
+int fp64_variant_count() { return sizeof(kVariantsF64) / sizeof(kVariantsF64[0]); }
+Variant fp64_variant(int idx) { return kVariantsF64[idx]; }
+int fp64_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
+    for (int v = 0; v < fp64_variant_count(); ++v) {
+        const Variant& x = kVariantsF64[v];
+        if (x.m_tile == m_tile && x.n_tile == n_tile && x.k_step == k_step && x.check_m == check_m &&
+            x.check_n == check_n)
+            return v;
+    }
+    return -1;
+}
+
+hipError_t launch_fp64(int idx, bool inject, const F64Args& a, hipStream_t s) {
+    if (idx != 0) return hipErrorInvalidValue;
+    const int ntm = (a.M + BM - 1) / BM, ntn = (a.N + BN - 1) / BN;
+    const dim3 grid((unsigned)(ntm * ntn)), block(NT);
+#define FTGEMM_LAUNCH(FTL, INJL) hipLaunchKernelGGL((ftgemm_f64_kernel<FTL, INJL>), grid, block, 0, s, a)
+    if (inject) {
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, true);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, true);
+        else FTGEMM_LAUNCH(2, true);
+    } else {
+        if (a.ft_level == 0) FTGEMM_LAUNCH(0, false);
+        else if (a.ft_level == 1) FTGEMM_LAUNCH(1, false);
+        else FTGEMM_LAUNCH(2, false);
+    }
+#undef FTGEMM_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_scale64(double* C, int64_t ldc, int32_t M, int32_t N, double beta, hipStream_t s) {
+    const int64_t total = (int64_t)M * N;
+    const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    hipLaunchKernelGGL(scale64_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, C, ldc, M, N, beta);
+    return hipGetLastError();
+}
+
+}  // namespace ftgemm_impl

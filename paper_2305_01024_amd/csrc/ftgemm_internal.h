@@ -93,6 +93,32 @@ int fp8_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_
 hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_fp8_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);
 
+// ---- FP64 (A, B, C as double) ----
+struct F64Args {
+    const double* A;
+    const double* B;
+    double* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    double alpha, beta;
+    float tol_c;                 // threshold factor c
+    int32_t check_interval;      // g, in k-steps
+    int32_t ft_level;            // 0, 1, 2
+    int32_t problem;             // problem index reported in events (0)
+    ftgemm_event_t* events;
+    uint32_t* counters;
+    int32_t event_cap;
+    const ftgemm_fault_t* faults;
+    int32_t n_faults;
+    ftgemm_fault_log_t* fault_log;
+    int32_t fault_log_cap;
+};
+int fp64_variant_count();
+Variant fp64_variant(int idx);
+int fp64_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
+hipError_t launch_fp64(int idx, bool inject, const F64Args& a, hipStream_t stream);
+hipError_t launch_scale64(double* C, int64_t ldc, int32_t M, int32_t N, double beta, hipStream_t stream);
+
 // ---- batched persistent launch ----
 // Device descriptor of one problem of a batched call.
 struct BatchProblem {

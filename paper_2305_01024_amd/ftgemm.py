@@ -16,7 +16,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libftgemm.so")
 
-F32, BF16, F8E4M3 = 0, 1, 2
+F32, BF16, F8E4M3, F64 = 0, 1, 2, 3
 FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
 FT_RECOMPUTE = 0x10   # OR-ed into FT_DETECT or FT_CORRECT: recompute the tiles that end possibly wrong
 OK, UNCORRECTABLE, INVALID, UNSUPPORTED, HIP_ERROR, NO_MEMORY, LOG_OVERFLOW = 0, 1, -1, -2, -3, -4, -5
@@ -107,6 +107,9 @@ def lib():
                                  ctypes.POINTER(Report)]
         L.ftgemm_run_nonfused.argtypes = [vp, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
                                           ctypes.POINTER(Report)]
+        f64 = ctypes.c_double
+        L.ftgemm_run_f64.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, i32, f64, vp,
+                                     ctypes.POINTER(Report)]
         L.ftgemm_set_injection.argtypes = [vp, vp, i32]
         L.ftgemm_get_injection_log.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
         L.ftgemm_batched.argtypes = [vp, i32, vp, i32, f32, vp, ctypes.POINTER(Report)]
@@ -120,7 +123,7 @@ def lib():
         for name in ("ftgemm_create", "ftgemm_destroy", "ftgemm_set_scales", "ftgemm_set_config",
                      "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
                      "ftgemm_get_injection_log", "ftgemm_batched", "ftgemm_batched_config", "ftgemm_tune", "ftgemm_get_tuned",
-                     "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused"):
+                     "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused", "ftgemm_run_f64"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -186,6 +189,17 @@ def ftgemm_run(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: i
     st = lib().ftgemm_run(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
                           report.ptr() if report is not None else None)
     return _check(st, "ftgemm_run")
+
+
+def ftgemm_run_f64(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: int, B: int, ldb: int,
+                   beta: float, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
+                   stream: int = 0, report: ReportBuffer | None = None) -> int:
+    """FP64 C = alpha A B + beta C on device pointers to double (column-major),
+    for a handle created with F64.  Returns the status (0 or 1); raises
+    FtgemmError on negative statuses."""
+    st = lib().ftgemm_run_f64(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
+                              report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_run_f64")
 
 
 def ftgemm_run_nonfused(handle: int, m: int, n: int, k: int, A: int, lda: int, B: int, ldb: int, C: int,

@@ -46,6 +46,18 @@ def normal(shape, workload: int, stream: int) -> np.ndarray:
     return np.asfortranarray(g.standard_normal(size=shape, dtype=np.float32))
 
 
+def uniform64(shape, workload: int, stream: int, lo=-1.0, hi=1.0) -> np.ndarray:
+    """i.i.d. U[lo, hi) in FP64 (full 53-bit mantissas), column-major."""
+    g = rng(workload, stream)
+    return np.asfortranarray(g.uniform(lo, hi, size=shape))
+
+
+def normal64(shape, workload: int, stream: int) -> np.ndarray:
+    """i.i.d. N(0, 1) in FP64 (full 53-bit mantissas), column-major."""
+    g = rng(workload, stream)
+    return np.asfortranarray(g.standard_normal(size=shape))
+
+
 def heavy_tailed(shape, workload: int, stream: int, frac=0.01, scale=100.0) -> np.ndarray:
     """N(0, 1) with a Bernoulli(frac) mask of entries multiplied by ``scale``
     (mask drawn from the same stream, after the values)."""

@@ -91,13 +91,13 @@ def check_cfg(cfg):
     return (cm, cn, cfg[2], cfg[3])
 
 
-def replay_against_gpu(A, B, cfg, rep, log, C0=None, alpha=1.0, beta=0.0, ft_level=2, tiles=None):
+def replay_against_gpu(A, B, cfg, rep, log, C0=None, alpha=1.0, beta=0.0, ft_level=2, tiles=None, u=O.U_FP32):
     """Replay the run on the oracle with the GPU's applied faults.  Faults the
     oracle classifies grey (either decision is valid) take the GPU's decision;
     returns (ReplayResult, classes of the first pass, n_grey, n_grey_invalid)."""
     cc = check_cfg(cfg)
     rc = O.ReplayConfig(mc=cc[0], nc=cc[1], ku=cc[2], g=cc[3], c=float(rep.report.tol_used),
-                        ft_level=ft_level)
+                        ft_level=ft_level, u=u)
     inj = log_to_injections(log)
     res = O.replay(A, B, rc, C0=C0, alpha=alpha, beta=beta, injections=inj, tiles=tiles)
     grey = np.where(res.classes["cls"] == O.CLS_GREY)[0]

@@ -435,3 +435,33 @@ def test_decode_bf16_all_codes_vs_torch():
     ok = ~np.isnan(ref)
     assert np.array_equal(np.isnan(ref), np.isnan(got))
     assert np.array_equal(ref[ok], got[ok])
+
+
+# ---------------------------------------------------------------------------
+# binary64 roundoff (the FP64 path replays with u = 2^-53)
+# ---------------------------------------------------------------------------
+def test_fp64_roundoff_clean_runs_raise_nothing():
+    """At u = 2^-53 the threshold still bounds the oracle's own binary64
+    residuals: no event on clean N(0,1), heavy-tailed and positive data,
+    a check after every k-step, ragged tiles."""
+    for s, gen in enumerate((W.normal64, W.heavy_tailed, W.uniform64)):
+        A, B = gen((40, 200), 99, 2 * s), gen((200, 36), 99, 2 * s + 1)
+        res = O.replay(A, B, O.ReplayConfig(mc=16, nc=16, ku=8, g=1, u=O.U_FP64, c=2.0))
+        assert res.n_events == 0, gen.__name__
+
+
+def test_fp64_threshold_sees_what_fp32_cannot():
+    """A +1e-6 fault on N(0,1) data: far below the binary32 threshold (about
+    1e-2 here, so benign and kept), far above the binary64 one (about 1e-10,
+    so located and corrected at its site); u enters the threshold."""
+    A, B = W.normal64((32, 64), 100, 0), W.normal64((64, 32), 100, 1)
+    clean = O.gemm(A, B)
+    inj = O.make_injections([(1, 0, 3, 5, 7, 0.0, 1e-6)])
+    r32 = O.replay(A, B, O.ReplayConfig(mc=16, nc=16, ku=8, g=1, u=O.U_FP32, c=2.0), injections=inj)
+    assert r32.n_events == 0 and r32.classes[0]["cls"] == O.CLS_BENIGN
+    assert abs(r32.C[16 + 5, 7] - clean[16 + 5, 7] - 1e-6) < 1e-12
+    r64 = O.replay(A, B, O.ReplayConfig(mc=16, nc=16, ku=8, g=1, u=O.U_FP64, c=2.0), injections=inj)
+    assert r64.classes[0]["cls"] == O.CLS_MUST and r64.n_events == 1
+    e = r64.events[0]
+    assert (e["tile_m"], e["tile_n"], e["kstep"], e["row"], e["col"], e["kind"]) == (1, 0, 3, 5, 7, O.EV_CORRECTED)
+    assert np.max(np.abs(r64.C - clean)) < 1e-12
