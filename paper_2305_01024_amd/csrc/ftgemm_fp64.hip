@@ -12,7 +12,10 @@
 //   * encodings of each staged panel (Eq. 1-2) from the staging registers:
 //       w[k] = sum_i A[i,k]: every wave holds one whole column of the A panel
 //       per load slot, reduced across the wave;
-//       v[k] = sum_j B[k,j]: per wave partial sums, added when read;
+//       v[k] = sum_j B[k,j]: a lane reduction per wave, then one LDS atomic
+//       add per wave (three rotating slots);
+//     the lane reductions use DPP moves and permlane swaps on the two
+//     32-bit halves of each double (no LDS round trip);
 //   * reference checksums (Eq. 3-4): threads 0..127 own rows (R_i, ||a_i||^2),
 //     threads 128..255 own columns (S_j, ||b_j||^2);
 //   * a check every `check_interval` k-steps and after the last: row and
@@ -39,7 +42,7 @@ struct F64Lds {
     double As[2][BK][LP];         // A panel, k-major (i contiguous)
     double Bs[2][BK][LP];         // B panel, k-major (j contiguous)
     double wsum[2][BK];           // e^T A of the panel
-    double vpart[2][4][BK];       // B e of the panel, per wave
+    double vsum[3][BK];           // B e of the panel (added across waves, 3 rotating slots)
     double rowsum[BM];            // row sums of the tile
     double colpart[4][BN];        // column sums per wave (each wave holds 4 row groups)
     double nsum[4];               // per-wave sums of ||a_i|| (waves 0, 1) and ||b_j|| (waves 2, 3)
@@ -50,10 +53,46 @@ struct F64Lds {
     int nf;
 };
 
+// Lane exchanges of a double on its two 32-bit halves.  dpp64<CTRL>: the
+// value of the DPP-selected lane.  swap_sum64<BIT>: own value plus that of
+// lane l ^ (1 << BIT) for BIT = 4 or 5 (v_permlane16/32_swap with both
+// operands the value itself returns the own value in one result and the
+// partner's in the other, so their sum is the pair's sum).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int BIT>
+__device__ __forceinline__ double swap_sum64(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    unsigned a0, a1, b0, b1;
+    if constexpr (BIT == 4) {
+        const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a0 = rl[0]; a1 = rl[1]; b0 = rh[0]; b1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a0 = rl[0]; a1 = rl[1]; b0 = rh[0]; b1 = rh[1];
+    }
+    const double d0 = __longlong_as_double((long long)(((unsigned long long)b0 << 32) | a0));
+    const double d1 = __longlong_as_double((long long)(((unsigned long long)b1 << 32) | a1));
+    return d0 + d1;
+}
+// Sum over the 64 lanes of a wave, in every lane.  Ascending levels: after
+// bits 0 .. b-1 are summed, the partners quad_perm [3,2,1,0] (l ^ 3) and
+// row_half_mirror (l ^ 7 within 8) hold the same value as l ^ 2 and l ^ 4.
 __device__ __forceinline__ double wave_sum64(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp64<0xB1>(x);    // quad_perm [1,0,3,2]: l ^ 1
+    x += dpp64<0x1B>(x);    // quad_perm [3,2,1,0]
+    x += dpp64<0x141>(x);   // row_half_mirror
+    x += dpp64<0x128>(x);   // row_ror:8: l ^ 8
+    x = swap_sum64<4>(x);
+    return swap_sum64<5>(x);
 }
 
 __device__ __forceinline__ double flip64(double v, int bit) {
@@ -128,7 +167,7 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, int vslot) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int k = 4 * r + wave, i = 2 * lane;
@@ -146,18 +185,17 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
                 if (lane == 0) s.wsum[buf][4 * r + wave] = w;
             }
             // B e: the thread's 4 columns of its k pair, then the 8 lanes of
-            // the wave with the same k pair (lane bits 3..5)
+            // the wave with the same k pair (lane bits 3..5), then the waves
             double v0 = 0.0, v1 = 0.0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) { v0 += rb[r][0]; v1 += rb[r][1]; }
-#pragma unroll
-            for (int off = 8; off <= 32; off <<= 1) {
-                v0 += __shfl_xor(v0, off, 64);
-                v1 += __shfl_xor(v1, off, 64);
-            }
+            v0 += dpp64<0x128>(v0);   // row_ror:8: exactly l ^ 8 within a row
+            v1 += dpp64<0x128>(v1);
+            v0 = swap_sum64<5>(swap_sum64<4>(v0));
+            v1 = swap_sum64<5>(swap_sum64<4>(v1));
             if (lane < 8) {
-                s.vpart[buf][wave][2 * lane] = v0;
-                s.vpart[buf][wave][2 * lane + 1] = v1;
+                atomicAdd(&s.vsum[vslot][2 * lane], v0);
+                atomicAdd(&s.vsum[vslot][2 * lane + 1], v1);
             }
         }
     };
@@ -317,12 +355,18 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         __syncthreads();   // s.bc is rewritten by the next check
     };
 
+    if constexpr (FT > 0) {
+        if (tid < 3 * BK) (&s.vsum[0][0])[tid] = 0.0;
+        __syncthreads();
+    }
     load(0);
-    store(0);
+    store(0, 0);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
         const int cur = t & 1;
         if (t + 1 < nk) load(t + 1);
+        // slot of panel t + 2: its last reader (step t - 1) finished before this step
+        if (FT > 0 && t + 2 < nk && tid < BK) s.vsum[(t + 2) % 3][tid] = 0.0;
         // the product of this k-step, one k at a time (outer products)
 #pragma unroll 4
         for (int k = 0; k < BK; ++k) {
@@ -341,14 +385,12 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
 #pragma unroll
             for (int k = 0; k < BK; ++k) {
                 const double x = row_owner ? s.As[cur][k][own] : s.Bs[cur][k][own];
-                const double y = row_owner ? (s.vpart[cur][0][k] + s.vpart[cur][1][k]) +
-                                                 (s.vpart[cur][2][k] + s.vpart[cur][3][k])
-                                           : s.wsum[cur][k];
+                const double y = row_owner ? s.vsum[t % 3][k] : s.wsum[cur][k];
                 ref = fma(x, y, ref);
                 nrm2 = fma(x, x, nrm2);
             }
         }
-        if (t + 1 < nk) store(cur ^ 1);
+        if (t + 1 < nk) store(cur ^ 1, (t + 1) % 3);
         if constexpr (INJ) {   // faults of k-step t hit the accumulator after its update
             while (fnext < s.nf && s.fault[fnext].kstep == t) {
                 const ftgemm_fault_t f = s.fault[fnext];
