@@ -3,9 +3,12 @@
 // C = alpha * A * B + beta * C in binary64, A, B, C column-major.  On MI355X
 // the FP64 vector FMA rate equals the FP64 matrix-core rate, so this kernel
 // keeps the paper's own outer-product SIMT form (section 3, 8 x 8 thread
-// tiles): a workgroup of 256 threads computes a 128 x 128 tile, each thread an 8 x 8 micro-tile
-// (rows 8 ty .. 8 ty + 7, columns 8 tx .. 8 tx + 7, tid = 16 ty + tx) with
-// v_fma_f64, k-steps of 16 staged through double-buffered LDS.
+// tiles): a workgroup of 256 threads computes a 128 x 128 tile, each thread an
+// 8 x 8 micro-tile with v_fma_f64, k-steps of 16 staged through
+// double-buffered LDS.  tid = 16 ty + tx holds rows 32 (r / 2) + 2 ty + r % 2
+// and columns 32 (c / 2) + 2 tx + c % 2 (r, c = 0..7): each 16-byte fragment
+// read of a wave then covers 16 consecutive pairs (no LDS bank conflicts),
+// where contiguous 8-wide micro-tiles would put 16 lanes 64 bytes apart.
 //
 // Fault tolerance, threadblock-level (section 4.2.3), online (section 2.2,
 // Eq. 4), all in FP64:
@@ -44,7 +47,7 @@ struct F64Lds {
     double wsum[2][BK];           // e^T A of the panel
     double vsum[3][BK];           // B e of the panel (added across waves, 3 rotating slots)
     double rowsum[BM];            // row sums of the tile
-    double colpart[4][BN];        // column sums per wave (each wave holds 4 row groups)
+    double colpart[4][BN];        // column sums per wave (each wave holds four ty)
     double nsum[4];               // per-wave sums of ||a_i|| (waves 0, 1) and ||b_j|| (waves 2, 3)
     int census[4][4];             // per wave: #rows, first row, #cols, first col flagged
     double bc[5];                 // first flagged row: R, r, tau; first flagged column: r, tau
@@ -94,6 +97,11 @@ __device__ __forceinline__ double wave_sum64(double x) {
     x = swap_sum64<4>(x);
     return swap_sum64<5>(x);
 }
+
+// micro-tile index maps (see the header comment)
+__device__ __forceinline__ int tile_row(int ty, int r) { return 32 * (r >> 1) + 2 * ty + (r & 1); }
+__device__ __forceinline__ int line_owner(int i) { return (i & 31) >> 1; }       // ty (or tx) holding line i
+__device__ __forceinline__ int line_slot(int i) { return 2 * (i >> 5) + (i & 1); }  // r (or c) of line i
 
 __device__ __forceinline__ double flip64(double v, int bit) {
     return __longlong_as_double(__double_as_longlong(v) ^ (long long)(1ull << (bit & 63)));
@@ -202,7 +210,7 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
 
     // ---- online check after k-step t (kp = k indices accumulated) ----
     auto check = [&](int t, int kp) {
-        // row sums (over the 16 threads tx of a row group: lane bits 0..3)
+        // row sums (over the 16 threads tx of one ty: lane bits 0..3)
         double rs[TPT], cs[TPT];
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
@@ -228,11 +236,11 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             for (int off = 16; off <= 32; off <<= 1) cs[c] += __shfl_xor(cs[c], off, 64);
         if (tx == 0) {
 #pragma unroll
-            for (int r = 0; r < TPT; ++r) s.rowsum[TPT * ty + r] = rs[r];
+            for (int r = 0; r < TPT; ++r) s.rowsum[tile_row(ty, r)] = rs[r];
         }
         if ((lane >> 4) == 0) {
 #pragma unroll
-            for (int c = 0; c < TPT; ++c) s.colpart[wave][TPT * tx + c] = cs[c];
+            for (int c = 0; c < TPT; ++c) s.colpart[wave][tile_row(tx, c)] = cs[c];
         }
         const double nv = sqrt(nrm2);
         const double ws = wave_sum64(nv);
@@ -294,8 +302,8 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         if (!row_owner && own == fc) { s.bc[3] = res; s.bc[4] = tau; }
         __syncthreads();
         if (correct) {
-            // P_ij = R_i - sum_{j' != j} P_ij': the 16 threads of row group fr / 8
-            const int fry = fr / TPT, frr = fr % TPT, fcx = fc / TPT, fcc = fc % TPT;
+            // P_ij = R_i - sum_{j' != j} P_ij': the 16 threads (one ty) holding row fr
+            const int fry = line_owner(fr), frr = line_slot(fr), fcx = line_owner(fc), fcc = line_slot(fc);
             double part = 0.0, oldv = 0.0;
             const bool mine_row = ty == fry;
 #pragma unroll
@@ -372,9 +380,9 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         for (int k = 0; k < BK; ++k) {
             double av[TPT], bv[TPT];
 #pragma unroll
-            for (int r = 0; r < TPT; ++r) av[r] = s.As[cur][k][TPT * ty + r];
+            for (int r = 0; r < TPT; ++r) av[r] = s.As[cur][k][tile_row(ty, r)];
 #pragma unroll
-            for (int c = 0; c < TPT; ++c) bv[c] = s.Bs[cur][k][TPT * tx + c];
+            for (int c = 0; c < TPT; ++c) bv[c] = s.Bs[cur][k][tile_row(tx, c)];
 #pragma unroll
             for (int r = 0; r < TPT; ++r)
 #pragma unroll
@@ -394,8 +402,8 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         if constexpr (INJ) {   // faults of k-step t hit the accumulator after its update
             while (fnext < s.nf && s.fault[fnext].kstep == t) {
                 const ftgemm_fault_t f = s.fault[fnext];
-                const bool owner = f.row / TPT == ty && f.col / TPT == tx;
-                const int fr = f.row % TPT, fc = f.col % TPT;
+                const bool owner = line_owner(f.row) == ty && line_owner(f.col) == tx;
+                const int fr = line_slot(f.row), fc = line_slot(f.col);
                 double oldv = 0.0, newv = 0.0;
 #pragma unroll
                 for (int r = 0; r < TPT; ++r)
@@ -434,10 +442,10 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
     // epilogue: C = alpha P + beta C (beta == 0: C is not read)
 #pragma unroll
     for (int c = 0; c < TPT; ++c) {
-        const int j = TPT * tx + c;
+        const int j = tile_row(tx, c);
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
-            const int i = TPT * ty + r;
+            const int i = tile_row(ty, r);
             if (i < mI && j < nJ) {
                 double* pc = a.C + (size_t)(j0 + j) * a.ldc + (i0 + i);
                 double v = a.alpha * acc[r][c];
