@@ -151,6 +151,10 @@ def test_select_config_follows_the_measured_best_tile_and_checks_every_256_k():
     for dtype in (F.BF16, F.F8E4M3):
         c = F.ftgemm_select_config(dtype, 8192, 8192, 8192)
         assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)
+    # FP64: the one compiled configuration, a check every 256 k, for any shape and level
+    for (m, n) in [(8192, 8192), (1, 1), (3001, 1999)]:
+        for level in (F.FT_OFF, F.FT_DETECT, F.FT_CORRECT):
+            assert F.ftgemm_select_config(F.F64, m, n, 512, level).as_tuple() == (128, 128, 16, 16, 128, 128)
 
 
 def test_status_strings():
