@@ -192,3 +192,26 @@ def test_unsupported_combinations(h):
         F.ftgemm_set_injection(h, None)
     finally:
         F.ftgemm_destroy(h32)
+
+
+def test_leading_dimensions_and_padding_untouched(h):
+    """lda > m, ldb > k, ldc > m: the product lands in C's m x n block, the
+    padding rows of C keep their values."""
+    import torch
+    m, n, k = 200, 150, 100
+    lda, ldb, ldc = 256, 128, 240
+    A = W.normal64((m, k), 709, 0)
+    B = W.normal64((k, n), 709, 1)
+    C0 = W.normal64((ldc, n), 709, 2)
+    Ap = np.zeros((lda, k)); Ap[:m] = A
+    Bp = np.zeros((ldb, n)); Bp[:k] = B
+    dA = torch.from_numpy(np.ascontiguousarray(Ap.T)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(Bp.T)).cuda()
+    dC = torch.from_numpy(np.ascontiguousarray(C0.T)).cuda()
+    rep = F.ReportBuffer(16)
+    st = F.ftgemm_run_f64(h, m, n, k, 1.0, dA.data_ptr(), lda, dB.data_ptr(), ldb, 0.5, dC.data_ptr(), ldc,
+                          F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream, rep)
+    C = dC.cpu().numpy().T
+    assert st == F.OK and rep.report.n_events == 0
+    assert rel_fro(C[:m], O.gemm(A, B, C0[:m], beta=0.5)) <= TOL_F64
+    assert np.array_equal(C[m:], C0[m:])

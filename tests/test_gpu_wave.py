@@ -224,6 +224,33 @@ def test_many_bit_flips_ragged(h, cfg):
     assert rel_fro(C, res.C) <= TOL_F32
 
 
+@pytest.mark.parametrize("cfg", WAVE_CFGS)
+def test_alpha_beta_with_faults(h, cfg):
+    """alpha = 0.5, beta = -1.25 with C0: one fault in each of three
+    wavefront tiles; the oracle replay with the same alpha, beta and C0 gives
+    the same events and C."""
+    m, n, k = 384, 320, 416
+    A = W.uniform((m, k), 610, 0)
+    B = W.uniform((k, n), 610, 1)
+    C0 = W.uniform((m, n), 610, 2)
+    rows = [(0, 0, 2, 3, 4, W.KIND_ADD, 1e3, 0), (3, 2, 7, 60, 1, W.KIND_ADD, -1e3, 0),
+            (5, 4, 12, 10, 63, W.KIND_ADD, 1e3, 0)]
+    sites = np.zeros(len(rows), dtype=F.FAULT_DTYPE)
+    for q, r in enumerate(rows):
+        sites[q] = r
+    F.ftgemm_set_config(h, cfg)
+    F.ftgemm_set_injection(h, sites)
+    try:
+        st, C, rep = run(h, A, B, C0, alpha=0.5, beta=-1.25)
+        log = F.ftgemm_get_injection_log(h)
+    finally:
+        F.ftgemm_set_injection(h, None)
+    res, cls, n_grey, bad = replay_against_gpu(A, B, cfg, rep, log, C0=C0, alpha=0.5, beta=-1.25)
+    assert bad == 0 and st == F.OK and rep.report.corrected == 3
+    assert event_keys(rep.events) == event_keys(res.events)
+    assert rel_fro(C, O.gemm(A, B, C0, alpha=0.5, beta=-1.25)) <= TOL_F32
+
+
 def test_sites_outside_their_check_tile_are_not_applied(h):
     """A site whose row or column lies beyond its wavefront tile addresses no
     element of it: nothing is applied, nothing is flagged."""
