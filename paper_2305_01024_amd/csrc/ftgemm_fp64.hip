@@ -86,16 +86,19 @@ __device__ __forceinline__ double swap_sum64(double x) {
     const double d1 = __longlong_as_double((long long)(((unsigned long long)b1 << 32) | a1));
     return d0 + d1;
 }
-// Sum over the 64 lanes of a wave, in every lane.  Ascending levels: after
-// bits 0 .. b-1 are summed, the partners quad_perm [3,2,1,0] (l ^ 3) and
-// row_half_mirror (l ^ 7 within 8) hold the same value as l ^ 2 and l ^ 4.
-__device__ __forceinline__ double wave_sum64(double x) {
+// Sum over the 16 lanes of a row (lane bits 0..3), in every lane of it.
+// Ascending levels: after bits 0 .. b-1 are summed, the partners
+// quad_perm [3,2,1,0] (l ^ 3) and row_half_mirror (l ^ 7 within 8) hold the
+// same value as l ^ 2 and l ^ 4.
+__device__ __forceinline__ double row_sum64(double x) {
     x += dpp64<0xB1>(x);    // quad_perm [1,0,3,2]: l ^ 1
     x += dpp64<0x1B>(x);    // quad_perm [3,2,1,0]
     x += dpp64<0x141>(x);   // row_half_mirror
-    x += dpp64<0x128>(x);   // row_ror:8: l ^ 8
-    x = swap_sum64<4>(x);
-    return swap_sum64<5>(x);
+    return x + dpp64<0x128>(x);   // row_ror:8: l ^ 8
+}
+// Sum over the 64 lanes of a wave, in every lane.
+__device__ __forceinline__ double wave_sum64(double x) {
+    return swap_sum64<5>(swap_sum64<4>(row_sum64(x)));
 }
 
 // micro-tile index maps (see the header comment)
@@ -227,13 +230,9 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             cs[c] = x;
         }
 #pragma unroll
-        for (int r = 0; r < TPT; ++r)
+        for (int r = 0; r < TPT; ++r) rs[r] = row_sum64(rs[r]);
 #pragma unroll
-            for (int off = 1; off <= 8; off <<= 1) rs[r] += __shfl_xor(rs[r], off, 64);
-#pragma unroll
-        for (int c = 0; c < TPT; ++c)
-#pragma unroll
-            for (int off = 16; off <= 32; off <<= 1) cs[c] += __shfl_xor(cs[c], off, 64);
+        for (int c = 0; c < TPT; ++c) cs[c] = swap_sum64<5>(swap_sum64<4>(cs[c]));
         if (tx == 0) {
 #pragma unroll
             for (int r = 0; r < TPT; ++r) s.rowsum[tile_row(ty, r)] = rs[r];
@@ -315,8 +314,7 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
                     part += (in_row && !hit) ? acc[r][c] : 0.0;
                     oldv = hit ? acc[r][c] : oldv;
                 }
-#pragma unroll
-            for (int off = 1; off <= 8; off <<= 1) part += __shfl_xor(part, off, 64);
+            part = row_sum64(part);
             const double newv = s.bc[0] - part;
             const bool owner = mine_row && tx == fcx;
 #pragma unroll
