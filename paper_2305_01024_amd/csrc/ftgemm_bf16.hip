@@ -5,8 +5,13 @@
 namespace ftgemm_impl {
 namespace {
 
+// The 128 x 128 tile (79 KB of LDS) fits two workgroups per compute unit;
+// asking for two wavefronts per SIMD holds its FT kernels to 256 VGPRs
+// (unbounded they take 284, one wavefront per SIMD).
+template <int BM, int BN, int FT>
+constexpr int kMinWavesBF16 = (BM == 128 && BN == 128 && FT > 0) ? 2 : 1;
 template <int BM, int BN, int BK, int WM, int WN, int FT, bool INJ>
-__global__ __launch_bounds__(64 * WM * WN) void ftgemm_bf16_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(64 * WM * WN, (kMinWavesBF16<BM, BN, FT>)) void ftgemm_bf16_kernel(LaunchArgs a) {
     __shared__ bf16::SmemBF16<BM, BN, BK, WM, WN> sm;
     const int ntm = (a.M + BM - 1) / BM;
     bf16::tile<BM, BN, BK, WM, WN, FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, sm);
@@ -49,12 +54,19 @@ hipError_t launch_shape_bf16(bool inject, const LaunchArgs& a, hipStream_t s) {
 
 constexpr Variant kVariantsBF16[] = {
     {256, 256, 64, 256, 256},
+    {128, 128, 64, 128, 128},
+};
+// default-selection cost model (aligned with kVariantsBF16; MI355X, 8192^3)
+constexpr VariantModel kModelsBF16[] = {
+    {1, 8, 994.0f, 505.0f},
+    {2, 4, 786.0f, 337.0f},
 };
 
 }  // namespace
 
 int bf16_variant_count() { return sizeof(kVariantsBF16) / sizeof(kVariantsBF16[0]); }
 Variant bf16_variant(int idx) { return kVariantsBF16[idx]; }
+VariantModel bf16_variant_model(int idx) { return kModelsBF16[idx]; }
 int bf16_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n) {
     for (int v = 0; v < bf16_variant_count(); ++v) {
         const Variant& x = kVariantsBF16[v];
@@ -68,6 +80,7 @@ int bf16_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check
 hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t s) {
     switch (idx) {
         case 0: return launch_shape_bf16<256, 256, 64, 2, 4>(inject, a, s);
+        case 1: return launch_shape_bf16<128, 128, 64, 2, 2>(inject, a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -75,6 +88,7 @@ hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t s)
 hipError_t launch_bf16_retry(int idx, const LaunchArgs& a, int grid, hipStream_t s) {
     switch (idx) {
         case 0: return launch_shape_bf16_retry<256, 256, 64, 2, 4>(a, grid, s);
+        case 1: return launch_shape_bf16_retry<128, 128, 64, 2, 2>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

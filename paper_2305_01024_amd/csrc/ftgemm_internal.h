@@ -82,6 +82,7 @@ hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t
 // Kernel variants for BF16 operands (A, B as bfloat16 codes).
 int bf16_variant_count();
 Variant bf16_variant(int idx);
+VariantModel bf16_variant_model(int idx);
 int bf16_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 hipError_t launch_bf16(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_bf16_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);

@@ -151,6 +151,13 @@ def test_select_config_follows_the_measured_best_tile_and_checks_every_256_k():
     for dtype in (F.BF16, F.F8E4M3):
         c = F.ftgemm_select_config(dtype, 8192, 8192, 8192)
         assert (c.check_m, c.check_n) == (c.m_tile, c.n_tile)
+    # BF16, the same model with the BF16 tiles' measured rates: 128 x 128 where
+    # 256 x 256 tiles would leave most compute units idle (2048^3: 0.079 against
+    # 0.144 ms online), 256 x 256 from 3072 on (0.212 against 0.266 ms)
+    for N, t in {2048: 128, 3072: 256, 4096: 256, 8192: 256}.items():
+        for level in (F.FT_OFF, F.FT_CORRECT):
+            c = F.ftgemm_select_config(F.BF16, N, N, N, level)
+            assert (c.m_tile, c.n_tile, c.k_step * c.check_interval) == (t, t, 256), (N, level, c.as_tuple())
     # FP64: the one compiled configuration, a check every 256 k, for any shape and level
     for (m, n) in [(8192, 8192), (1, 1), (3001, 1999)]:
         for level in (F.FT_OFF, F.FT_DETECT, F.FT_CORRECT):
