@@ -37,6 +37,9 @@ MUTANTS = {
     "beta epilogue sign": ("AT(C, ldc, i0 + i, j0 + j) = cfg->alpha * P[i + j * mI] + c0;",
                            "AT(C, ldc, i0 + i, j0 + j) = cfg->alpha * P[i + j * mI] - c0;"),
     "row-norm accumulates |a| not a^2": ("q += a * a;", "q += fabs(a);"),
+    "row threshold ignores u (binary32 roundoff fixed)": (
+        "rbet[i] = oracle_beta(cfg->u, k1, nJ, sqrt(na2[i]), sum_nb);",
+        "rbet[i] = oracle_beta(5.9604644775390625e-08, k1, nJ, sqrt(na2[i]), sum_nb);"),
 }
 
 
