@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2516.6
+PEAK_FP8_MFMA_TFLOPS = 5033.2
 PEAK_FP64_TFLOPS = 78.6      # FP64 vector FMA and FP64 matrix cores alike on MI355X
 METRIC = "FT-GEMM TFLOP/s & %MFMA peak vs plain GEMM (same GPU), overhead %, detect/correct rate"
 
@@ -51,9 +52,10 @@ def parse():
                         "problems in one persistent launch vs a loop of launches; irregular: tall-skinny, "
                         "small-K and odd shapes, autotuned vs fixed configuration; ablation: fused online "
                         "ABFT against the same checks run as separate launches (FP32 8192^3, beta = 0)")
-    p.add_argument("--dtype", choices=("f32", "bf16", "f64"), default="f32",
+    p.add_argument("--dtype", choices=("f32", "bf16", "fp8", "f64"), default="f32",
                    help="f32: the FP32 square workload (beta = 1); bf16: A, B heavy-tailed N(0,1) "
-                        "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel); f64: the binary64 "
+                        "rounded to bfloat16, beta = 0 (profiling of the BF16 kernel); fp8: the same "
+                        "operands scaled per tensor to E4M3, alpha = the product of the two scales; f64: the binary64 "
                         "path (ftgemm_run_f64), N(0,1) operands, beta = 1")
     p.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     p.add_argument("--skip-injection", action="store_true", help="do not run the injection-rate sweep")
@@ -136,15 +138,21 @@ def main():
         return bench_f64(args)
     N = args.size
     m = n = k = N
-    bf16 = args.dtype == "bf16"
+    lowp = args.dtype in ("bf16", "fp8")
+    alpha = 1.0
     log(f"generating {args.dtype} inputs {m}x{n}x{k}")
-    if bf16:
+    if lowp:
         A = W.heavy_tailed((m, k), 4, W.STREAM_A)
         B = W.heavy_tailed((k, n), 4, W.STREAM_B)
-        Ac, _ = W.quantize_bf16(A)
-        Bc, _ = W.quantize_bf16(B)
-        dA = torch.from_numpy(np.ascontiguousarray(Ac.T).view(np.int16)).cuda()
-        dB = torch.from_numpy(np.ascontiguousarray(Bc.T).view(np.int16)).cuda()
+        if args.dtype == "bf16":
+            (Ac, _), (Bc, _) = W.quantize_bf16(A), W.quantize_bf16(B)
+            dA = torch.from_numpy(np.ascontiguousarray(Ac.T).view(np.int16)).cuda()
+            dB = torch.from_numpy(np.ascontiguousarray(Bc.T).view(np.int16)).cuda()
+        else:
+            (Ac, sa), (Bc, sb) = W.quantize_e4m3(A), W.quantize_e4m3(B)
+            dA = torch.from_numpy(np.ascontiguousarray(Ac.T)).cuda()
+            dB = torch.from_numpy(np.ascontiguousarray(Bc.T)).cuda()
+            alpha = sa * sb
         C0 = np.zeros((m, n), np.float32, order="F")
         beta = 0.0
     else:
@@ -158,14 +166,14 @@ def main():
     dC = dC0.clone()
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
-    dtype = F.BF16 if bf16 else F.F32
-    peak = PEAK_BF16_MFMA_TFLOPS if bf16 else PEAK_FP32_MFMA_TFLOPS
+    dtype = {"f32": F.F32, "bf16": F.BF16, "fp8": F.F8E4M3}[args.dtype]
+    peak = {"f32": PEAK_FP32_MFMA_TFLOPS, "bf16": PEAK_BF16_MFMA_TFLOPS, "fp8": PEAK_FP8_MFMA_TFLOPS}[args.dtype]
     h = F.ftgemm_create(dtype, 0)
     cfg = F.ftgemm_select_config(dtype, m, n, k)
     flop = 2.0 * m * n * k
 
     def call(level, report=None):
-        return F.ftgemm_run(h, m, n, k, 1.0, dA.data_ptr(), m, dB.data_ptr(), k, beta, dC.data_ptr(), m,
+        return F.ftgemm_run(h, m, n, k, alpha, dA.data_ptr(), m, dB.data_ptr(), k, beta, dC.data_ptr(), m,
                             level, 0.0, sh, report)
 
     if args.probe:
@@ -229,7 +237,7 @@ def main():
 
     # fault injection at a rate per second of GEMM time, bit flips in bits 0..30
     injection = None
-    if not args.skip_injection and ms_ft and not bf16:
+    if not args.skip_injection and ms_ft and not lowp:
         injection = {}
         g = W.rng(2, W.STREAM_SITES)
         launches = 8
@@ -254,7 +262,7 @@ def main():
             log(f"injection {rate}/s: {agg}")
 
     cpu = None
-    if not args.skip_cpu and not bf16:
+    if not args.skip_cpu and not lowp:
         cpu = cpu_baseline(A, B, C0, cfg)
 
     F.ftgemm_destroy(h)
@@ -262,9 +270,12 @@ def main():
     tf = tf_ft if tf_ft else tf_plain
     kname = f"ftgemm_{args.dtype}_kernel<{cfg.m_tile},{cfg.n_tile},{cfg.k_step}>"
     traffic, traffic_src = measured_traffic(args.dtype, N) if ms_ft else (None, None)
-    if bf16:
+    if args.dtype == "bf16":
         workload = f"bf16 square FT-GEMM M=N=K={N}, A,B~N(0,1) with 1% x100, bf16 RNE, alpha=1, beta=0, " \
                    f"online detect+correct"
+    elif args.dtype == "fp8":
+        workload = f"fp8-e4m3 square FT-GEMM M=N=K={N}, A,B~N(0,1) with 1% x100, per-tensor power-of-two " \
+                   f"scale to E4M3 (RNE, saturating), alpha=scale_A*scale_B, beta=0, online detect+correct"
     else:
         workload = f"fp32 square FT-GEMM M=N=K={N}, A,B,C~N(0,1), alpha=1, beta=1, online detect+correct"
     out = {
@@ -659,6 +670,7 @@ def bench_granularity(h, m, n, k, fused, args, stream):
 KERNEL_SOURCES = {
     "f32": ("ftgemm_fp32.hip", "ftgemm_fp32.hpp", "ftgemm_abft.hpp", "ftgemm_internal.h"),
     "bf16": ("ftgemm_bf16.hip", "ftgemm_bf16.hpp", "ftgemm_abft.hpp", "ftgemm_internal.h"),
+    "fp8": ("ftgemm_fp8.hip", "ftgemm_fp8.hpp", "ftgemm_abft.hpp", "ftgemm_internal.h"),
 }
 
 
