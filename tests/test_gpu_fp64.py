@@ -215,3 +215,40 @@ def test_leading_dimensions_and_padding_untouched(h):
     assert st == F.OK and rep.report.n_events == 0
     assert rel_fro(C[:m], O.gemm(A, B, C0[:m], beta=0.5)) <= TOL_F64
     assert np.array_equal(C[m:], C0[m:])
+
+
+def test_full_size_8192_sampled_tiles(h):
+    """8192^3 N(0,1) A, B, C, alpha = beta = 1, as benchmarked: a clean run
+    raises no event and three sampled tiles (two corners, one inside) match
+    the binary64 oracle replay of those tiles; a run with one +1e3 fault per
+    tile corrects all 4096 of them, and on the sampled tiles the event log
+    equals the replay's and C matches it."""
+    m = n = k = 8192
+    A = W.normal64((m, k), 64, 0)
+    B = W.normal64((k, n), 64, 1)
+    C0 = W.normal64((m, n), 64, 2)
+    tiles = [(0, 0), (m // CFG[0] - 1, n // CFG[1] - 1), (37, 11)]
+    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
+
+    def sample(C):
+        return np.concatenate([C[tm * CFG[0]:(tm + 1) * CFG[0], tn * CFG[1]:(tn + 1) * CFG[1]].ravel()
+                               for tm, tn in tiles])
+
+    st, C, rep, _ = _run(h, A, B, C0, alpha=1.0, beta=1.0)
+    assert st == F.OK and rep.report.n_events == 0 and rep.report.checks == _checks(m, n, k)
+    rc = O.ReplayConfig(mc=CFG[0], nc=CFG[1], ku=CFG[2], g=CFG[3], c=float(rep.report.tol_used), u=O.U_FP64)
+    clean = O.replay(A, B, rc, C0=C0, alpha=1.0, beta=1.0, tiles=tiles)
+    assert clean.n_events == 0
+    assert rel_fro(sample(C), sample(clean.C)) <= TOL_F64
+
+    sites = W.fault_sites(W.rng(64, W.STREAM_SITES), m, n, k, *CFG, 0, payload=1e3, per_tile=1)
+    st, C, rep, log = _run(h, A, B, C0, alpha=1.0, beta=1.0, sites=sites, cap=8192)
+    assert st == F.OK and len(log) == len(sites) == (m // CFG[0]) * (n // CFG[1])
+    assert rep.report.corrected == len(sites) and rep.report.uncorrectable == 0
+    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
+    res, _, _, bad = replay_against_gpu(A, B, CFG, rep, part, C0=C0, alpha=1.0, beta=1.0, tiles=tiles,
+                                        u=O.U_FP64)
+    assert bad == 0 and len(part) == len(tiles)
+    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
+    assert event_keys(ev) == event_keys(res.events)
+    assert rel_fro(sample(C), sample(res.C)) <= TOL_F64
