@@ -251,3 +251,39 @@ def test_full_size_8192_sampled_tiles(h):
     for (tm, tn) in tiles:
         sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
         assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
+
+
+def test_full_size_8192_one_fault_per_tile(h):
+    """8192^3 N(0,1), beta = 1, automatic configuration, one +1e5 fault in
+    every one of the 1024 tiles at a seeded k-step, row and column: all are
+    corrected, and on three sampled tiles the oracle replay (same faults, same
+    threshold constant) classifies them must-detect, its event log equals the
+    GPU's and C matches it.  At this size the bound passes 1e3 about half way
+    through K (c 2u (K'+n+1) |a_i| sum_j |b_j| ~ 4e3 at K' = 8192 with c = 2
+    and 256 N(0,1) columns), so a +1e3 fault in the second half lies inside
+    the rounding bound and is left alone by design (465 of 1024 were
+    corrected in a run with that payload)."""
+    m = n = k = 8192
+    A = W.normal((m, k), 2, W.STREAM_A)
+    B = W.normal((k, n), 2, W.STREAM_B)
+    C0 = W.normal((m, n), 2, W.STREAM_C)
+    cfg = F.ftgemm_select_config(F.F32, m, n, k).as_tuple()
+    assert cfg[:2] == (256, 256)
+    sites = W.fault_sites(W.rng(8192, W.STREAM_SITES), m, n, k, *cfg[:4], 0, payload=1e5, per_tile=1)
+    F.ftgemm_set_injection(h, sites)
+    st, C, rep = run(h, A, B, C0, alpha=1.0, beta=1.0)
+    log = F.ftgemm_get_injection_log(h)
+    assert st == F.OK and rep.report.config.as_tuple()[:4] == cfg[:4]
+    assert len(log) == len(sites) == 1024
+    assert rep.report.corrected == 1024 and rep.report.uncorrectable == 0
+    tiles = [(0, 0), (31, 31), (13, 21)]
+    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
+    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, part, C0=C0, alpha=1.0, beta=1.0, tiles=tiles)
+    assert bad == 0 and len(part) == len(tiles)
+    assert np.all(cls["cls"] == O.CLS_MUST)
+    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
+    assert event_keys(ev) == event_keys(res.events)
+    for (tm, tn) in tiles:
+        sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
+        assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
