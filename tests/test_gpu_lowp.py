@@ -5,6 +5,8 @@ Frobenius error <= 2e-2 against the oracle on the quantised operands (the
 stated bound for BF16/FP8; the products are exact, so the measured error is
 the FP32 accumulation's, checked at 1e-5 too); event logs equal to the
 oracle replay's exactly."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -185,13 +187,22 @@ def test_fault_injection_exact_site_log(h, kind):
     assert rel_fro(C, res.C) <= TOL_ACC[h[1][4]]
 
 
+@functools.lru_cache(maxsize=1)
+def _full_operands(name):
+    """8192 x 8192 heavy-tailed N(0,1) operands (1% x100) quantised to the
+    dtype, shared by the full-size tests of that dtype."""
+    dt = DTYPES[name]
+    Ac, sa = _quant(dt, W.heavy_tailed((8192, 8192), 4, W.STREAM_A))
+    Bc, sb = _quant(dt, W.heavy_tailed((8192, 8192), 4, W.STREAM_B))
+    return Ac, sa, Bc, sb
+
+
 def test_full_size_8192_sampled_tiles(h):
     """8192^3 with heavy-tailed N(0,1) operands (1% x100), per-tensor
     power-of-two scaling: no event in a clean run, and sampled tiles match the
     oracle replay on the decoded operands."""
     m = n = k = 8192
-    Ac, sa = _quant(h[1], W.heavy_tailed((m, k), 4, W.STREAM_A))
-    Bc, sb = _quant(h[1], W.heavy_tailed((k, n), 4, W.STREAM_B))
+    Ac, sa, Bc, sb = _full_operands(h[1][4])
     st, C, rep = _run(h, Ac, Bc, sa, sb)
     cfg = rep.report.config.as_tuple()
     assert st == F.OK and rep.report.n_events == 0
@@ -199,6 +210,39 @@ def test_full_size_8192_sampled_tiles(h):
     A, B = _decoded(h, Ac, Bc)
     res = O.replay(A, B, O.ReplayConfig(mc=cfg[0], nc=cfg[1], ku=cfg[2], g=cfg[3]), alpha=sa * sb, tiles=tiles)
     assert res.n_events == 0
+    for (tm, tn) in tiles:
+        sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
+        assert rel_fro(C[sl], res.C[sl]) <= TOL_ACC[h[1][4]], (tm, tn)
+
+
+def test_full_size_8192_one_fault_per_tile(h):
+    """The full-size operands, automatic configuration, one +1e7 fault in
+    every tile at a seeded k-step, row and column, checked on the unscaled
+    codes (scales 1): every fault is corrected, and on three sampled tiles the
+    oracle replay classifies them must-detect, its event log equals the GPU's
+    and C matches it.  The bound at full K is about 4e5 here (heavy-tailed
+    rows: |a_i| ~ 900), so 1e7 is must-detect at every k-step."""
+    m = n = k = 8192
+    Ac, _, Bc, _ = _full_operands(h[1][4])
+    cfg = F.ftgemm_select_config(h[1][0], m, n, k).as_tuple()
+    ntiles = (m // cfg[0]) * (n // cfg[1])
+    sites = W.fault_sites(W.rng(8192, W.STREAM_SITES), m, n, k, *cfg[:4], 0, payload=1e7, per_tile=1)
+    F.ftgemm_set_injection(h[0], sites)
+    st, C, rep = _run(h, Ac, Bc)
+    log = F.ftgemm_get_injection_log(h[0])
+    F.ftgemm_set_injection(h[0], None)
+    assert st == F.OK and rep.report.config.as_tuple()[:4] == cfg[:4]
+    assert len(log) == len(sites) == ntiles
+    assert rep.report.corrected == ntiles and rep.report.uncorrectable == 0
+    tiles = [(0, 0), (m // cfg[0] - 1, n // cfg[1] - 1), (5, 17)]
+    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
+    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
+    A, B = _decoded(h, Ac, Bc)
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, part, tiles=tiles)
+    assert bad == 0 and len(part) == len(tiles)
+    assert np.all(cls["cls"] == O.CLS_MUST)
+    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
+    assert event_keys(ev) == event_keys(res.events)
     for (tm, tn) in tiles:
         sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
         assert rel_fro(C[sl], res.C[sl]) <= TOL_ACC[h[1][4]], (tm, tn)
