@@ -234,3 +234,24 @@ def test_tune_batched_measures_every_variant(h):
     import torch
     rates = F.ftgemm_tune_batched(h, torch.cuda.current_stream().cuda_stream)
     assert rates.shape == (3,) and np.all(rates > 1e11)
+
+
+def test_full_size_1024_problems_sampled(h):
+    """The benchmarked batch: 1024 problems, M, N, K log-uniform in
+    [32, 2048], FP32 and BF16 mixed, one persistent launch.  No event in the
+    clean run, every check counted, and 32 seeded sampled problems match the
+    oracle product."""
+    import torch
+    shapes = _shapes(1024, 32, 2048, 5)
+    bt = Batch(shapes, 5, beta=1.0)
+    rep = F.ReportBuffer(64)
+    st = F.ftgemm_batched(h, bt.probs, F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream, rep)
+    assert st == F.OK and rep.report.n_events == 0
+    expect = 0
+    for p, (m, n, k, _) in enumerate(shapes):
+        c = F.ftgemm_batched_config(h, p).as_tuple()
+        nk = -(-k // c[2])
+        expect += -(-m // c[0]) * -(-n // c[1]) * -(-nk // c[3])
+    assert rep.report.checks == expect
+    for p in W.rng(5, W.STREAM_SHAPES).choice(len(shapes), 32, replace=False):
+        assert rel_fro(bt.result(p), bt.reference(p)) <= TOL, (p, shapes[p])
