@@ -301,3 +301,40 @@ def test_graph_replays_match_eager(h):
         x = torch.randn(1024, 1024, device="cuda")
         (x @ x).sum().item()
     del graph
+
+
+@pytest.mark.parametrize("cfg", WAVE_CFGS)
+def test_full_size_8192_one_fault_per_wave_tile(h, cfg):
+    """8192^3 N(0,1), beta = 1, in the configuration the granularity benchmark
+    times: one +1e5 fault in each of the 16384 wavefront tiles (must-detect at
+    every k-step: the bound at full K is about 1e3 for 64 N(0,1) columns;
+    16384 events and log entries fill the handle's device logs exactly);
+    all are corrected, and on three sampled wavefront tiles the event log
+    equals the oracle replay's and C matches it."""
+    m = n = k = 8192
+    A = W.normal((m, k), 2, W.STREAM_A)
+    B = W.normal((k, n), 2, W.STREAM_B)
+    C0 = W.normal((m, n), 2, W.STREAM_C)
+    cm, cn, ku, g = check_cfg(cfg)
+    sites = W.fault_sites(W.rng(8192, 64), m, n, k, cm, cn, ku, g, 0, payload=1e5, per_tile=1)
+    F.ftgemm_set_config(h, cfg)
+    F.ftgemm_set_injection(h, sites)
+    try:
+        st, C, rep = run(h, A, B, C0, beta=1.0, cap=32768)
+        log = F.ftgemm_get_injection_log(h, 32768)
+    finally:
+        F.ftgemm_set_injection(h, None)
+    assert st == F.OK and len(log) == len(sites) == (m // cm) * (n // cn)
+    assert rep.report.corrected == len(sites) and rep.report.uncorrectable == 0
+    assert rep.report.checks == _n_checks(m, n, k, cfg)
+    tiles = [(0, 0), (m // cm - 1, n // cn - 1), (37, 90)]
+    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
+    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, part, C0=C0, beta=1.0, tiles=tiles)
+    assert bad == 0 and len(part) == len(tiles)
+    assert np.all(cls["cls"] == O.CLS_MUST)
+    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
+    assert event_keys(ev) == event_keys(res.events)
+    for (tm, tn) in tiles:
+        sl = (slice(tm * cm, (tm + 1) * cm), slice(tn * cn, (tn + 1) * cn))
+        assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
