@@ -27,6 +27,14 @@
  * K' the number of k indices accumulated so far (a standard gamma_n bound
  * for any-order summation, turned into norms by Cauchy-Schwarz).
  *
+ * The paper's checks assume finite operands (its fault model, section 4.1,
+ * covers errors in the computation, not in the data).  A tile whose operands
+ * hold Inf or NaN has non-finite norms, references and bounds, so no check
+ * can separate rounding from a fault there: the replay reports such a tile
+ * once (kind ORACLE_EV_NONFINITE, at the first check that sees the value),
+ * locates and corrects nothing in it, and leaves its part of C to IEEE
+ * arithmetic.
+ *
  * All arithmetic is FP64.  Matrices are column-major with leading
  * dimensions, as in BLAS.  Parallelism is OpenMP over independent output
  * columns (plain GEMM) or output tiles (replay); every per-element sum runs
@@ -140,7 +148,8 @@ enum {
     ORACLE_EV_CHECKSUM_ROW = 2,   /* one row flagged, no column */
     ORACLE_EV_CHECKSUM_COL = 3,   /* one column flagged, no row */
     ORACLE_EV_UNCORRECTABLE = 4,  /* any other non-empty pattern */
-    ORACLE_EV_DETECTED = 5        /* detect-only level: any non-empty pattern */
+    ORACLE_EV_DETECTED = 5,       /* detect-only level: any non-empty pattern */
+    ORACLE_EV_NONFINITE = 6       /* the tile's operands hold Inf or NaN: no decision possible */
 };
 
 typedef struct {
@@ -207,6 +216,7 @@ static void replay_tile(const oracle_cfg_t* cfg, int64_t tm, int64_t tn,
 
     int64_t next_inj = 0;        /* injections of this tile, sorted by kstep */
     int64_t first_open = 0;      /* first injection not yet evaluated by a check */
+    int nonfinite = 0;           /* a non-finite operand has been reported for this tile */
 
     for (int64_t t = 0; t < nk; ++t) {
         const int64_t k0 = t * ku;
@@ -268,6 +278,27 @@ static void replay_tile(const oracle_cfg_t* cfg, int64_t tm, int64_t tn,
         double sum_na = 0.0, sum_nb = 0.0;
         for (int64_t i = 0; i < mI; ++i) sum_na += sqrt(na2[i]);
         for (int64_t j = 0; j < nJ; ++j) sum_nb += sqrt(nb2[j]);
+
+        /* An Inf or NaN among the operands read so far makes the norms, the
+         * reference checksums and the bound non-finite: the check can no longer
+         * tell rounding from a fault.  The tile is reported once, at the first
+         * check that sees it, with no location, nothing is corrected or
+         * re-based, and its part of C is whatever IEEE arithmetic gives.  The
+         * faults such a check would have seen are left unclassified. */
+        if (!isfinite(sum_na) || !isfinite(sum_nb)) {
+            for (int64_t q = first_open; q < next_inj; ++q)
+                if (cls) cls[inj_idx[q]].check_step = t;
+            first_open = next_inj;
+            if (!nonfinite) {
+                oracle_event_t e;
+                memset(&e, 0, sizeof e);
+                e.tile_m = tm; e.tile_n = tn; e.kstep = t; e.row = -1; e.col = -1;
+                e.kind = ORACLE_EV_NONFINITE;
+                ev_push(evs, &e);
+                nonfinite = 1;
+            }
+            continue;
+        }
         int64_t nr = 0, ncf = 0, fr = -1, fc = -1;
         for (int64_t i = 0; i < mI; ++i) {
             double s = 0.0;

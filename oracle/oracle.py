@@ -26,6 +26,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libftgemm_oracle.so")
 
 EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED = 1, 2, 3, 4, 5
+EV_NONFINITE = 6      # operands of the tile hold Inf/NaN: reported once, no decision
 CLS_BENIGN, CLS_GREY, CLS_MUST = 0, 1, 2
 
 U_FP32 = 2.0 ** -24   # unit roundoff of IEEE binary32 (round to nearest)

@@ -40,6 +40,9 @@ MUTANTS = {
     "row threshold ignores u (binary32 roundoff fixed)": (
         "rbet[i] = oracle_beta(cfg->u, k1, nJ, sqrt(na2[i]), sum_nb);",
         "rbet[i] = oracle_beta(5.9604644775390625e-08, k1, nJ, sqrt(na2[i]), sum_nb);"),
+    "non-finite operands go through the decision table": (
+        "if (!isfinite(sum_na) || !isfinite(sum_nb)) {", "if (0) {"),
+    "non-finite tile reported at every check": ("            if (!nonfinite) {\n", "            if (1) {\n"),
 }
 
 

@@ -465,3 +465,73 @@ def test_fp64_threshold_sees_what_fp32_cannot():
     e = r64.events[0]
     assert (e["tile_m"], e["tile_n"], e["kstep"], e["row"], e["col"], e["kind"]) == (1, 0, 3, 5, 7, O.EV_CORRECTED)
     assert np.max(np.abs(r64.C - clean)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# non-finite operands (the paper's checks assume finite data; reading: a tile
+# whose operands hold Inf or NaN is reported once, nothing is located or
+# corrected there, and C is what IEEE arithmetic gives)
+# ---------------------------------------------------------------------------
+def _py_gemm(A, B):
+    """Brute-force product in pure Python floats (IEEE binary64, ascending k)."""
+    m, k = A.shape
+    n = B.shape[1]
+    out = np.zeros((m, n))
+    for i in range(m):
+        for j in range(n):
+            s = 0.0
+            for p in range(k):
+                s += float(A[i, p]) * float(B[p, j])
+            out[i, j] = s
+    return out
+
+
+def _same_ieee(X, Y):
+    return (np.array_equal(np.isnan(X), np.isnan(Y)) and np.array_equal(np.isinf(X), np.isinf(Y))
+            and np.array_equal(X[np.isinf(X)], Y[np.isinf(Y)])
+            and np.allclose(X[np.isfinite(X)], Y[np.isfinite(Y)], rtol=0, atol=1e-12))
+
+
+@pytest.mark.parametrize("where,value", [("A", math.nan), ("A", math.inf), ("B", -math.inf), ("B", math.nan)])
+def test_nonfinite_operand_reported_once_per_tile_and_c_is_ieee(where, value):
+    A, B, cfg = _tiny_problem()            # 6 x 5 x 7, tiles 4+2 x 3+2, k-steps 3+3+1, a check every step
+    A, B = A.astype(np.float64), B.astype(np.float64)
+    if where == "A":
+        A[5, 4] = value                    # row 5 -> tile row 1; k = 4 -> k-step 1
+        want = {(1, 0), (1, 1)}
+    else:
+        B[3, 1] = value                    # column 1 -> tile column 0; k = 3 -> k-step 1
+        want = {(0, 0), (1, 0)}
+    res = O.replay(A, B, cfg)
+    keys = sorted((int(e["tile_m"]), int(e["tile_n"]), int(e["kstep"]), int(e["row"]), int(e["col"]),
+                   int(e["kind"])) for e in res.events)
+    assert keys == sorted((tm, tn, 1, -1, -1, O.EV_NONFINITE) for (tm, tn) in want)
+    assert _same_ieee(res.C, _py_gemm(A, B))
+
+
+def test_nonfinite_tile_does_not_stop_corrections_elsewhere():
+    A, B, cfg = _tiny_problem()
+    A, B = A.astype(np.float64), B.astype(np.float64)
+    A[5, 0] = math.nan                     # tile row 1 non-finite from k-step 0
+    clean = _py_gemm(A, B)
+    inj = O.make_injections([(0, 1, 2, 3, 1, 0.0, 1e3), (1, 0, 1, 0, 0, 0.0, 1e3)])
+    res = O.replay(A, B, cfg, injections=inj)
+    keys = sorted((int(e["tile_m"]), int(e["tile_n"]), int(e["kstep"]), int(e["row"]), int(e["col"]),
+                   int(e["kind"])) for e in res.events)
+    assert keys == [(0, 1, 2, 3, 1, O.EV_CORRECTED), (1, 0, 0, -1, -1, O.EV_NONFINITE),
+                    (1, 1, 0, -1, -1, O.EV_NONFINITE)]
+    # the finite tile is corrected; the fault in the non-finite tile stays (row 4, column 0
+    # holds a finite value plus 1e3, since only row 5 carries the NaN)
+    assert res.classes[0]["cls"] == O.CLS_MUST and res.classes[1]["cls"] == -1
+    want = clean.copy()
+    want[4, 0] += 1e3
+    assert _same_ieee(res.C, want)
+
+
+def test_nonfinite_operand_at_detect_only_level():
+    A, B, cfg = _tiny_problem()
+    A, B = A.astype(np.float64), B.astype(np.float64)
+    B[6, 4] = math.inf                     # column 4 -> tile column 1; k = 6 -> last k-step
+    res = O.replay(A, B, O.ReplayConfig(mc=cfg.mc, nc=cfg.nc, ku=cfg.ku, g=1, ft_level=1))
+    keys = sorted((int(e["tile_m"]), int(e["tile_n"]), int(e["kstep"]), int(e["kind"])) for e in res.events)
+    assert keys == [(0, 1, 2, O.EV_NONFINITE), (1, 1, 2, O.EV_NONFINITE)]
