@@ -235,31 +235,24 @@ def main():
             "recomputed": int(rep.report.recomputed), "recompute_failed": int(rep.report.recompute_failed)}
         log(f"levels: {levels}")
 
-    # fault injection at a rate per second of GEMM time, bit flips in bits 0..30
+    # fault injection at a rate per second of GEMM time (bits 0..30, and the
+    # exponent bits 23..30 alone)
     injection = None
     if not args.skip_injection and ms_ft and not lowp:
-        injection = {}
-        g = W.rng(2, W.STREAM_SITES)
-        launches = 8
-        for rate in (10, 100, 1000):
-            counts, total = W.rate_schedule(g, rate, ms_ft * 1e-3, launches)
-            agg = None
-            t_inj = []
-            for c_l in counts:
-                sites = W.fault_sites(g, m, n, k, cfg.m_tile, cfg.n_tile, cfg.k_step, cfg.check_interval,
-                                      int(c_l), kind=W.KIND_XOR)
-                F.ftgemm_set_injection(h, sites if len(sites) else None)
-                t_inj.append(timed(lambda: call(F.FT_CORRECT), 1, 0, stream))
-                rep = F.ReportBuffer(4096)
-                call(F.FT_CORRECT, rep)
-                flog = F.ftgemm_get_injection_log(h) if len(sites) else np.zeros(0, F.FAULT_LOG_DTYPE)
-                cl = classify(flog, rep.events, rep.report.tol_used)
-                agg = cl if agg is None else {kk: agg[kk] + cl[kk] for kk in agg}
-            F.ftgemm_set_injection(h, None)
-            agg["ms_per_step"] = float(np.mean(t_inj))
-            agg["overhead_vs_clean_pct"] = 100.0 * (agg["ms_per_step"] / ms_ft - 1.0)
-            injection[f"{rate}/s"] = agg
-            log(f"injection {rate}/s: {agg}")
+        injection = injection_sweep(h, call, cfg, m, n, k, ms_ft, stream, args)
+
+    # section 5.5: online against offline (detect-only + recompute) ABFT under
+    # the paper's error model, at 2048^3, 4096^3 and this size
+    online_offline = None
+    if not args.skip_injection and ms_ft and ms_plain and not lowp and levels:
+        online_offline = {}
+        for size in sorted({2048, 4096, N}):
+            if size == N:
+                online_offline[str(size)] = online_vs_offline(h, call, cfg, size, ms_plain, levels["detect_only"]["ms"],
+                                                              ms_ft, stream, args)
+            else:
+                online_offline[str(size)] = online_vs_offline_at(size, stream, args)
+            log(f"online vs offline {size}: {online_offline[str(size)]}")
 
     cpu = None
     if not args.skip_cpu and not lowp:
@@ -306,6 +299,7 @@ def main():
                      "kernel": kname + (" FT=2" if ms_ft else " FT=0")},
         "levels": levels,
         "injection": injection,
+        "online_vs_offline": online_offline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -674,6 +668,154 @@ KERNEL_SOURCES = {
 }
 
 
+def _flip_bit(old_v, new_v) -> int:
+    """Bit position a logged XOR fault flipped (from the two FP32 values)."""
+    x = int(np.float32(old_v).view(np.uint32)) ^ int(np.float32(new_v).view(np.uint32))
+    return x.bit_length() - 1 if x else -1
+
+
+def injection_sweep(h, call, cfg, m, n, k, ms_ft, stream, args, launches=50):
+    """Bit flips in accumulator lanes at 10 / 100 / 1000 faults per second of
+    GEMM time (the injection experiment of section 5.3, at this GPU's speed):
+    for each rate, round(rate * t * launches) faults spread over `launches`
+    launches of the injection build, at most one per tile and check interval,
+    at uniform (k-step, row, column, bit).  Two bit sets: bits 0..30 (the
+    workload's fault model, where most flips of low mantissa bits lie inside
+    the rounding bound and are benign) and the exponent bits 23..30 alone (so
+    that must-detect faults occur, and the detect and correct rates are
+    measured, at every rate).  Counts per class and per bit position.  The
+    correction cost is the time per launch against the injection build with
+    a site that never hits (same kernel, same instrumentation, no fault);
+    the instrumentation cost is that build against the production kernel."""
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    never = np.zeros(1, dtype=F.FAULT_DTYPE)
+    never[0] = (0, 0, 0, 0, 0, W.KIND_ADD, 1.0, 1)     # problem 1: no tile of this call matches it
+    F.ftgemm_set_injection(h, never)
+    ms_inj_clean = timed(lambda: call(F.FT_CORRECT), args.steps, args.warmup, stream)
+    out = {"launches_per_rate": launches, "ms_injection_build_no_fault": round(ms_inj_clean, 4),
+           "instrumentation_overhead_pct": round(100.0 * (ms_inj_clean / ms_ft - 1.0), 3)}
+    fields = ("injected", "must", "must_corrected", "benign", "benign_flagged", "grey", "grey_corrected")
+    for bits_name, bits in (("bits_0_30", range(0, 31)), ("bits_23_30", range(23, 31))):
+        g = W.rng(2, W.STREAM_SITES)
+        res = {}
+        for rate in (10, 100, 1000):
+            counts, total = W.rate_schedule(g, rate, ms_ft * 1e-3, launches)
+            agg = None
+            by_bit = {}
+            t_inj = []
+            for c_l in counts:
+                sites = W.fault_sites(g, m, n, k, cfg.m_tile, cfg.n_tile, cfg.k_step, cfg.check_interval,
+                                      int(c_l), kind=W.KIND_XOR, bits=bits) if c_l else never
+                F.ftgemm_set_injection(h, sites)
+                t_inj.append(timed(lambda: call(F.FT_CORRECT), 1, 0, stream))
+                rep = F.ReportBuffer(4096)
+                call(F.FT_CORRECT, rep)
+                flog = F.ftgemm_get_injection_log(h) if c_l else np.zeros(0, F.FAULT_LOG_DTYPE)
+                cl = classify(flog, rep.events, rep.report.tol_used)
+                agg = cl if agg is None else {kk: agg[kk] + cl[kk] for kk in agg}
+                for q in range(len(flog)):
+                    b = _flip_bit(flog[q]["old_v"], flog[q]["new_v"])
+                    one = classify(flog[q:q + 1], rep.events, rep.report.tol_used)
+                    row = by_bit.setdefault(str(b), [0] * len(fields))
+                    for q, name in enumerate(fields):
+                        row[q] += one[name]
+            agg["by_bit"] = {"fields": list(fields), **{b: by_bit[b] for b in sorted(by_bit, key=int)}}
+            agg["ms_per_step"] = round(float(np.mean(t_inj)), 4)
+            agg["correction_overhead_pct"] = round(100.0 * (agg["ms_per_step"] / ms_inj_clean - 1.0), 3)
+            res[f"{rate}/s"] = agg
+            log(f"injection {bits_name} {rate}/s: { {kk: v for kk, v in agg.items() if kk != 'by_bit'} }")
+        out[bits_name] = res
+    F.ftgemm_set_injection(h, None)
+    return out
+
+
+def _offline_model(tiles, t_plain, t_det, t_online, t_retry_extra, q, gamma0=1.0 / 256):
+    """Section 5.5's model: every tile accumulation fails with probability
+    gamma0, so a whole run fails with gamma = 1 - (1 - gamma0)^tiles; the
+    offline (detect-only) scheme restarts the whole product on a failure and
+    needs (1 - gamma) / (1 - 2 gamma) runs in expectation (no finite
+    expectation for gamma >= 1/2), the online scheme one.  Also the
+    tile-level recompute built here (only the flagged tiles run again):
+    expected extra time of its retry launch, measured with q flagged tiles
+    (q = tiles * gamma0 rounded, at least one).  The crossover gamma0* is
+    where the offline expectation equals the online time."""
+    gamma = 1.0 - (1.0 - gamma0) ** tiles
+    runs = (1.0 - gamma) / (1.0 - 2.0 * gamma) if gamma < 0.5 else None
+    r = t_online / t_det
+    gamma_star = (r - 1.0) / (2.0 * r - 1.0)
+    gamma0_star = 1.0 - (1.0 - gamma_star) ** (1.0 / tiles)
+    return {"tiles": int(tiles), "gamma0": gamma0, "gamma": round(gamma, 6),
+            "offline_expected_runs": round(runs, 4) if runs is not None else "unbounded (gamma >= 1/2)",
+            "ms_plain": round(t_plain, 4), "ms_detect_only": round(t_det, 4), "ms_online": round(t_online, 4),
+            "ms_offline_expected": round(t_det * runs, 4) if runs is not None else None,
+            "ms_detect_only_tile_recompute_expected": round(t_det + t_retry_extra, 4),
+            "tile_recompute_measured_with_flagged_tiles": int(q),
+            "online_overhead_pct": round(100.0 * (t_online / t_plain - 1.0), 3),
+            "detect_only_overhead_pct": round(100.0 * (t_det / t_plain - 1.0), 3),
+            "crossover_gamma0": float(f"{gamma0_star:.3e}")}
+
+
+def _retry_extra(h, call, cfg, N, q, stream, args):
+    """Extra time of the recompute launch with q flagged tiles at the
+    detect-only level: the injection build with q must-detect faults (one per
+    tile) and recompute on, against the same build with a fault that never hits."""
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    never = np.zeros(1, dtype=F.FAULT_DTYPE)
+    never[0] = (0, 0, 0, 0, 0, W.KIND_ADD, 1.0, 1)
+    F.ftgemm_set_injection(h, never)
+    t0 = timed(lambda: call(F.FT_DETECT | F.FT_RECOMPUTE), 5, 1, stream)
+    ntm, ntn = -(-N // cfg.m_tile), -(-N // cfg.n_tile)
+    g = W.rng(55, W.STREAM_SITES)
+    pick = np.sort(g.choice(ntm * ntn, size=q, replace=False))
+    sites = np.zeros(q, dtype=F.FAULT_DTYPE)
+    for x, t in enumerate(pick):
+        sites[x] = (t // ntn, t % ntn, 0, 1, 2, W.KIND_ADD, 1e6, 0)
+    F.ftgemm_set_injection(h, sites)
+    t1 = timed(lambda: call(F.FT_DETECT | F.FT_RECOMPUTE), 5, 1, stream)
+    rep = F.ReportBuffer(64)
+    call(F.FT_DETECT | F.FT_RECOMPUTE, rep)
+    F.ftgemm_set_injection(h, None)
+    assert rep.report.recomputed == q and rep.report.recompute_failed == 0, (rep.report.recomputed, q)
+    return max(0.0, t1 - t0)
+
+
+def online_vs_offline(h, call, cfg, N, ms_plain, ms_det, ms_online, stream, args, gamma0=1.0 / 256):
+    tiles = -(-N // cfg.m_tile) * -(-N // cfg.n_tile)
+    q = max(1, int(round(tiles * gamma0)))
+    extra = _retry_extra(h, call, cfg, N, q, stream, args)
+    return _offline_model(tiles, ms_plain, ms_det, ms_online, extra, q, gamma0)
+
+
+def online_vs_offline_at(N, stream, args, gamma0=1.0 / 256):
+    """online_vs_offline on the FP32 square workload at N^3 (N(0,1), beta = 1)."""
+    import torch
+
+    from paper_2305_01024_amd import ftgemm as F
+    from paper_2305_01024_amd import workloads as W
+
+    dA = torch.from_numpy(np.ascontiguousarray(W.normal((N, N), 2, W.STREAM_A).T)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(W.normal((N, N), 2, W.STREAM_B).T)).cuda()
+    dC = torch.from_numpy(np.ascontiguousarray(W.normal((N, N), 2, W.STREAM_C).T)).cuda()
+    h = F.ftgemm_create(F.F32, 0)
+    sh = stream.cuda_stream
+
+    def call(level, report=None):
+        return F.ftgemm_run(h, N, N, N, 1.0, dA.data_ptr(), N, dB.data_ptr(), N, 1.0, dC.data_ptr(), N, level, 0.0,
+                            sh, report)
+    try:
+        cfg = F.ftgemm_select_config(F.F32, N, N, N)
+        t_plain = timed(lambda: call(F.FT_OFF), args.steps, args.warmup, stream)
+        t_det = timed(lambda: call(F.FT_DETECT), args.steps, args.warmup, stream)
+        t_onl = timed(lambda: call(F.FT_CORRECT), args.steps, args.warmup, stream)
+        return online_vs_offline(h, call, cfg, N, t_plain, t_det, t_onl, stream, args, gamma0)
+    finally:
+        F.ftgemm_destroy(h)
+
+
 def kernel_source_hash(dtype: str) -> str:
     """sha256 over the device sources of the kernel the bench times."""
     import hashlib
@@ -705,36 +847,61 @@ def measured_traffic(dtype: str, size: int):
     return int(round(fetch + write)), os.path.relpath(path, ROOT)
 
 
-def cpu_baseline(A, B, C0, cfg, target_s: float = 12.0):
-    """The FP64 oracle replay (online ABFT, same tile decomposition) on a
-    bounded sample of the workload's output tiles, scaled to TFLOP/s."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, B, C0, cfg, target_s: float = 12.0, single_s: float = 5.0):
+    """The FP64 oracle replay (online ABFT, same tile decomposition and
+    checks) on a bounded sample of the workload's output tiles, distinct tiles
+    drawn by a seeded permutation, scaled to TFLOP/s: once on every host
+    thread, once on one thread."""
     from oracle import oracle as O
+    from paper_2305_01024_amd import workloads as W
 
     m, k = A.shape
     n = B.shape[1]
     rc = O.ReplayConfig(mc=cfg.m_tile, nc=cfg.n_tile, ku=cfg.k_step, g=cfg.check_interval)
     ntm, ntn = -(-m // cfg.m_tile), -(-n // cfg.n_tile)
-    threads = O.threads()
-    log(f"cpu baseline: oracle replay on sampled tiles, {threads} threads")
+    order = np.random.default_rng(W.seed(2, 5)).permutation(ntm * ntn)
     A64 = np.asfortranarray(A, dtype=np.float64)
     B64 = np.asfortranarray(B, dtype=np.float64)
     C64 = np.asfortranarray(C0, dtype=np.float64)
 
     def sample(count):
-        tiles = [((7 * i) % ntm, (13 * i + 3) % ntn) for i in range(count)]
+        tiles = [(int(t) % ntm, int(t) // ntm) for t in order[:count]]
         t0 = time.perf_counter()
         O.replay(A64, B64, rc, C0=C64, alpha=1.0, beta=1.0, tiles=tiles)
         return time.perf_counter() - t0, tiles
 
-    dt, tiles = sample(threads)
-    count = max(threads, int(threads * target_s / max(dt, 1e-3)))
-    count = min(count, ntm * ntn)
-    if count > threads:
-        dt, tiles = sample(count)
-    flop = 2.0 * cfg.m_tile * cfg.n_tile * k * len(tiles)
-    return {"value": round(flop / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(tiles)} of {ntm * ntn} output tiles ({cfg.m_tile}x{cfg.n_tile}, full K={k}) "
-                      f"replayed in FP64 with online checks, {dt:.1f} s"}
+    def leg(threads, budget):
+        O.set_threads(threads)
+        dt, tiles = sample(threads)
+        count = min(ntm * ntn, max(threads, int(threads * budget / max(dt, 1e-3))))
+        if count > threads:
+            dt, tiles = sample(count)
+        flop = 2.0 * cfg.m_tile * cfg.n_tile * k * len(tiles)
+        return flop / dt / 1e12, len(tiles), dt
+
+    threads = O.threads()
+    log(f"cpu baseline: oracle replay on sampled tiles, {threads} threads, then 1")
+    try:
+        v_all, n_all, dt_all = leg(threads, target_s)
+        v_one, n_one, dt_one = leg(1, single_s)
+    finally:
+        O.set_threads(threads)
+    desc = f"({cfg.m_tile}x{cfg.n_tile}, full K={k}, distinct tiles of a seeded permutation of all {ntm * ntn})"
+    return {"value": round(v_all, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_all} output tiles {desc} replayed in FP64 with online checks, {dt_all:.1f} s",
+            "single_core": {"value": round(v_one, 6), "unit": "TFLOP/s", "cores": 1,
+                            "sample": f"{n_one} output tiles, {dt_one:.1f} s"},
+            "cpu_model": _cpu_model()}
 
 
 if __name__ == "__main__":

@@ -33,8 +33,9 @@
  * Return codes: FTGEMM_OK (0); FTGEMM_UNCORRECTABLE (1, success with a
  * warning: at least one tile saw more than one fault in a check interval, C
  * may be wrong there and the events say where; with FTGEMM_FT_RECOMPUTE:
- * a recomputed tile flagged again); negative values are errors
- * listed in enum ftgemm_status.  A handle is not thread-safe; use one handle
+ * a recomputed tile flagged again); FTGEMM_NONFINITE_INPUT (2, success with
+ * a warning: A or B holds Inf or NaN, the tiles reading it were reported and
+ * not checked); negative values are errors listed in enum ftgemm_status.  A handle is not thread-safe; use one handle
  * per stream.
  */
 #ifndef FTGEMM_H
@@ -49,7 +50,8 @@ extern "C" {
 
 typedef struct ftgemm_ctx* ftgemm_t;
 
-enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2, FTGEMM_F64 = 3 };
+/* FTGEMM_C64: double complex, (re, im) binary64 pairs (ftgemm_run_z64). */
+enum ftgemm_dtype { FTGEMM_F32 = 0, FTGEMM_BF16 = 1, FTGEMM_F8E4M3 = 2, FTGEMM_F64 = 3, FTGEMM_C64 = 4 };
 
 /* ft_level: 0 = plain GEMM (fault tolerance compiled out of the kernel);
  * 1 = detect only, one check of the accumulated tile at the end of the
@@ -72,6 +74,10 @@ enum ftgemm_level { FTGEMM_FT_OFF = 0, FTGEMM_FT_DETECT = 1, FTGEMM_FT_CORRECT =
 enum ftgemm_status {
     FTGEMM_OK = 0,
     FTGEMM_UNCORRECTABLE = 1,
+    FTGEMM_NONFINITE_INPUT = 2,  /* success with a warning: A or B holds Inf/NaN; the tiles that read
+                                    it were reported (FTGEMM_EV_NONFINITE), not checked, and their C
+                                    is what IEEE arithmetic gives.  FTGEMM_UNCORRECTABLE takes
+                                    precedence when both apply. */
     FTGEMM_INVALID = -1,       /* invalid argument; report->bad_arg names it */
     FTGEMM_UNSUPPORTED = -2,   /* dtype, level or device not supported */
     FTGEMM_HIP_ERROR = -3,     /* a HIP runtime call failed */
@@ -84,7 +90,14 @@ enum ftgemm_event_kind {
     FTGEMM_EV_CHECKSUM_ROW = 2,   /* one row flagged, no column: row checksum re-based */
     FTGEMM_EV_CHECKSUM_COL = 3,   /* one column flagged, no row: column checksum re-based */
     FTGEMM_EV_UNCORRECTABLE = 4,  /* any other pattern: checksums re-based, C left as computed */
-    FTGEMM_EV_DETECTED = 5        /* detect-only level: any flagged pattern */
+    FTGEMM_EV_DETECTED = 5,       /* detect-only level: any flagged pattern */
+    FTGEMM_EV_NONFINITE = 6       /* the check tile's operands hold Inf or NaN: the bound and the
+                                     references are not finite, so rounding cannot be told from a
+                                     fault (the single-event-upset model of section 4.1 covers
+                                     faults in the computation on finite data).  Logged once per
+                                     check tile, at the first check whose k prefix holds the value,
+                                     with row = col = -1; nothing is located, corrected or
+                                     re-based there and the tile is not recomputed. */
 };
 
 enum ftgemm_fault_kind { FTGEMM_FAULT_ADD = 0, FTGEMM_FAULT_XOR = 1 };
@@ -109,12 +122,15 @@ typedef struct {
     int32_t problem;
 } ftgemm_fault_t;
 
-/* An applied fault: the site, the accumulator value before/after, and the
- * residuals and thresholds of its row and column at the first check that saw
- * it (check_step; -1 if no check ran after it). */
+/* An applied fault: the site, the accumulator value before/after (rounded to
+ * float), the residuals and thresholds of its row and column at the first
+ * check that saw it (check_step; -1 if no check ran after it), and delta =
+ * after - before in binary64 (exact for binary32 accumulators; the binary64
+ * difference for binary64 ones). */
 typedef struct {
     int32_t problem, tile_m, tile_n, kstep, row, col, kind, check_step;
-    float old_v, new_v, r_row, r_col, tau_row, tau_col, pad0_, pad1_;
+    float old_v, new_v, r_row, r_col, tau_row, tau_col;
+    double delta;
 } ftgemm_fault_log_t;
 
 /* Kernel configuration: compute tile m_tile x n_tile (one workgroup), k-step
@@ -135,11 +151,13 @@ typedef struct {
 } ftgemm_config_t;
 
 typedef struct {
-    uint64_t checks;          /* tile checks performed */
+    uint64_t checks;          /* check-tile checks performed, counted on the device (the
+                                 recompute launch's included) */
     uint64_t detected;        /* checks that flagged anything */
     uint64_t corrected;       /* FTGEMM_EV_CORRECTED events */
     uint64_t uncorrectable;   /* FTGEMM_EV_UNCORRECTABLE events */
     uint64_t checksum_only;   /* FTGEMM_EV_CHECKSUM_ROW/COL events */
+    uint64_t nonfinite_input; /* FTGEMM_EV_NONFINITE events: check tiles whose operands hold Inf/NaN */
     uint32_t n_events;        /* events written to `events` (<= cap_events) */
     uint32_t cap_events;      /* set by the caller: capacity of `events` */
     ftgemm_event_t* events;   /* caller-owned host array, may be NULL */
@@ -208,8 +226,8 @@ int ftgemm_run(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
  * to C after the GEMM of chunk `kstep` (row/col within the 256 x 256 tile).
  * Events carry the chunk index as kstep.  The chunk GEMMs use the
  * configuration ftgemm_tune found for (m, n, check_k) at level 0, if any.
- * Uses a handle-owned workspace of
- * (ceil(m/256) + ceil(n/256)) * (k + m + n) + m + n floats, grown on demand. */
+ * Uses a handle-owned workspace of ceil(m/256) * (k + n) + ceil(n/256) * (k + m)
+ * + m + n + ceil(m/256) * ceil(n/256) floats, grown on demand. */
 int ftgemm_run_nonfused(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float alpha,
                         const void* A, int64_t lda, const void* B, int64_t ldb, float beta,
                         float* C, int64_t ldc, int check_k, float tol, hipStream_t stream,
@@ -230,6 +248,33 @@ int ftgemm_run_nonfused(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float 
 int ftgemm_run_f64(ftgemm_t handle, int64_t m, int64_t n, int64_t k, double alpha,
                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                    double* C, int64_t ldc, int ft_level, double tol, hipStream_t stream,
+                   ftgemm_report_t* report);
+
+/* C = alpha * A * B + beta * C in double complex for a handle created with
+ * FTGEMM_C64: A (m x k), B (k x n) and C (m x n) are column-major arrays of
+ * (re, im) binary64 pairs, device pointers as in ftgemm_run, with leading
+ * dimensions counted in complex elements; alpha and beta point to host
+ * (re, im) pairs.  Section 6 names double-precision complex among the data
+ * types for future work.  The product runs as two binary64 FT products: with
+ * the inner index of each complex product split in two real ones,
+ * Re(AB) = A' B' and Im(AB) = A'' B', where A' interleaves (Re A, -Im A),
+ * A'' interleaves (Im A, Re A) and B' is B's own storage read as a real
+ * 2k x n matrix; the checksum relations of the two products are the real
+ * and imaginary parts of the complex ones, so every component of C is
+ * checked, located and corrected on its own (a complex element is two real
+ * accumulator values; the single-event-upset model of section 4.1 applies to
+ * each).  Threshold: u = 2^-53 and 2K' products per component, with
+ * complex 2-norms (K' complex k indices accumulated).  A configuration's
+ * k_step counts real inner indices (2 per complex k).  Events and fault
+ * sites carry the component in `problem` (0 real part, 1 imaginary part);
+ * tile, k-step, row and column are those of the real products.  The
+ * handle's workspace grows on demand to 4 m k + 2 m n doubles (A', A'' and
+ * the two real accumulators; alpha and beta are applied by a final pass).
+ * ft_level 0, 1 or 2 (FTGEMM_FT_RECOMPUTE: FTGEMM_UNSUPPORTED).  Return codes
+ * and report as ftgemm_run. */
+int ftgemm_run_z64(ftgemm_t handle, int64_t m, int64_t n, int64_t k, const double* alpha,
+                   const void* A, int64_t lda, const void* B, int64_t ldb, const double* beta,
+                   void* C, int64_t ldc, int ft_level, double tol, hipStream_t stream,
                    ftgemm_report_t* report);
 
 /* One problem of a batched call: C = alpha * (scale_a A) (scale_b B) +
@@ -305,7 +350,9 @@ int ftgemm_tune_batched(ftgemm_t handle, hipStream_t stream, double* rates);
 int ftgemm_set_injection(ftgemm_t handle, const ftgemm_fault_t* faults, int n);
 
 /* Copy the applied-fault log of the last call into `out` (host array of cap
- * entries); *n receives the number of faults applied. */
+ * entries); *n receives the number of entries copied.  Returns
+ * FTGEMM_LOG_OVERFLOW if more faults were applied than were copied (the
+ * device log holds 16384 entries; `cap` may be smaller). */
 int ftgemm_get_injection_log(ftgemm_t handle, ftgemm_fault_log_t* out, int cap, int* n);
 
 const char* ftgemm_status_string(int status);

@@ -53,12 +53,13 @@ class _Cfg(ctypes.Structure):
                 ("pad_", ctypes.c_int32)]
 
 
+# comp: complex replay only, the component (0 real, 1 imaginary) of a fault or decision
 INJ_DTYPE = np.dtype([("tile_m", "<i8"), ("tile_n", "<i8"), ("kstep", "<i8"), ("row", "<i8"),
                       ("col", "<i8"), ("old_v", "<f8"), ("new_v", "<f8"), ("force", "<i4"),
-                      ("pad_", "<i4")])
+                      ("comp", "<i4")])
 EV_DTYPE = np.dtype([("tile_m", "<i8"), ("tile_n", "<i8"), ("kstep", "<i8"), ("row", "<i8"),
                      ("col", "<i8"), ("kind", "<i4"), ("n_rows", "<i4"), ("n_cols", "<i4"),
-                     ("pad_", "<i4"), ("value_before", "<f8"), ("value_after", "<f8"),
+                     ("comp", "<i4"), ("value_before", "<f8"), ("value_after", "<f8"),
                      ("r_row", "<f8"), ("r_col", "<f8"), ("tau_row", "<f8"), ("tau_col", "<f8")])
 CLS_DTYPE = np.dtype([("cls", "<i4"), ("pad_", "<i4"), ("check_step", "<i8"), ("delta", "<f8"),
                       ("tau_row", "<f8"), ("tau_col", "<f8"), ("beta_row", "<f8"),
@@ -108,8 +109,20 @@ def load(path: str | None = None):
     lib.oracle_ftgemm_replay.argtypes = [ctypes.POINTER(_Cfg), dp, i64, dp, i64, dp, i64, dp, i64,
                                          vp, i64, vp, i64, vp, vp, i64]
     lib.oracle_ftgemm_replay.restype = i64
+    lib.oracle_zgemm.argtypes = [i64, i64, i64, ctypes.c_double, ctypes.c_double, dp, i64, dp, i64,
+                                 ctypes.c_double, ctypes.c_double, dp, i64]
+    lib.oracle_zgemm.restype = ctypes.c_int
+    lib.oracle_zencode_col.argtypes = [i64, i64, dp, i64, dp]
+    lib.oracle_zencode_col.restype = None
+    lib.oracle_zencode_row.argtypes = [i64, i64, dp, i64, dp]
+    lib.oracle_zencode_row.restype = None
+    lib.oracle_zftgemm_replay.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double, dp, i64, dp, i64,
+                                          dp, i64, dp, i64, vp, i64, vp, i64, vp, vp, i64]
+    lib.oracle_zftgemm_replay.restype = i64
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_sizeof.argtypes = [ctypes.c_int]
     lib.oracle_sizeof.restype = i64
     for which, want in ((0, ctypes.sizeof(_Cfg)), (1, INJ_DTYPE.itemsize), (2, EV_DTYPE.itemsize),
@@ -200,6 +213,11 @@ def threads() -> int:
     return int(load().oracle_threads())
 
 
+def set_threads(n: int) -> None:
+    """OpenMP threads for later oracle calls from this thread."""
+    load().oracle_set_threads(int(n))
+
+
 def beta_bound(u, kprime, count, own_norm, other_norm_sum) -> float:
     """Roundoff bound on one checksum residual (see the C file's header)."""
     return load().oracle_beta(float(u), int(kprime), int(count), float(own_norm), float(other_norm_sum))
@@ -228,7 +246,7 @@ class ReplayResult:
 
 
 def make_injections(rows) -> np.ndarray:
-    """rows: iterable of (tile_m, tile_n, kstep, row, col, old_v, new_v[, force])."""
+    """rows: iterable of (tile_m, tile_n, kstep, row, col, old_v, new_v[, force[, comp]])."""
     rows = list(rows)
     out = np.zeros(len(rows), dtype=INJ_DTYPE)
     for q, r in enumerate(rows):
@@ -236,6 +254,7 @@ def make_injections(rows) -> np.ndarray:
         out[q]["row"], out[q]["col"] = r[3], r[4]
         out[q]["old_v"], out[q]["new_v"] = r[5], r[6]
         out[q]["force"] = r[7] if len(r) > 7 else -1
+        out[q]["comp"] = r[8] if len(r) > 8 else 0
     return out
 
 
@@ -262,7 +281,8 @@ def replay(A, B, cfg: ReplayConfig, C0=None, alpha=1.0, beta=0.0, injections=Non
     cls = np.zeros(len(inj), dtype=CLS_DTYPE)
     sel = None
     if tiles is not None:
-        sel = np.ascontiguousarray(np.asarray(tiles, dtype=np.int64).reshape(-1, 2))
+        # each tile once: tiles are replayed in parallel and write their own block of C
+        sel = np.ascontiguousarray(np.unique(np.asarray(tiles, dtype=np.int64).reshape(-1, 2), axis=0))
     ev = np.zeros(ev_cap, dtype=EV_DTYPE)
     total = lib.oracle_ftgemm_replay(
         ctypes.byref(c), _dp(A), max(m, 1), _dp(B), max(k, 1), _dp(C0a), max(C0a.shape[0], 1),
@@ -271,4 +291,92 @@ def replay(A, B, cfg: ReplayConfig, C0=None, alpha=1.0, beta=0.0, injections=Non
         cls.ctypes.data if len(inj) else None, ev.ctypes.data, ev_cap)
     if total < 0:
         raise ValueError(f"oracle_ftgemm_replay: invalid argument ({total})")
+    return ReplayResult(C=C, events=ev[:min(total, ev_cap)].copy(), classes=cls, n_events=int(total))
+
+
+# ---------------------------------------------------------------------------
+# complex binary64 (double-complex GEMM, the data type section 6 names as
+# future work): operands are numpy complex128 arrays, column-major
+# ---------------------------------------------------------------------------
+def _z(x) -> np.ndarray:
+    """Column-major complex128 copy."""
+    return np.asfortranarray(np.asarray(x, dtype=np.complex128))
+
+
+def _zp(a: np.ndarray):
+    """Pointer to the interleaved (re, im) doubles of a complex128 array."""
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def zgemm(A, B, C0=None, alpha=1.0, beta=0.0) -> np.ndarray:
+    """C = alpha*A*B + beta*C0 in complex binary64 (alpha, beta complex)."""
+    lib = load()
+    A = _z(A)
+    B = _z(B)
+    m, k = A.shape
+    n = B.shape[1]
+    if C0 is None:
+        if beta != 0:
+            raise ValueError("beta != 0 needs C0")
+        C = np.zeros((max(m, 1), n), dtype=np.complex128, order="F")
+    else:
+        C = _z(C0).copy(order="F")
+    al, be = complex(alpha), complex(beta)
+    rc = lib.oracle_zgemm(m, n, k, al.real, al.imag, _zp(A), max(m, 1), _zp(B), max(k, 1), be.real, be.imag,
+                          _zp(C), max(C.shape[0], 1))
+    if rc != 0:
+        raise ValueError(f"oracle_zgemm: invalid argument {-rc}")
+    return C[:m] if m == 0 else C
+
+
+def zencode_col(A) -> np.ndarray:
+    """Complex e^T A (Eq. 1), length k."""
+    lib = load()
+    A = _z(A)
+    w = np.zeros(A.shape[1], dtype=np.complex128)
+    lib.oracle_zencode_col(A.shape[0], A.shape[1], _zp(A), max(A.shape[0], 1), _zp(w))
+    return w
+
+
+def zencode_row(B) -> np.ndarray:
+    """Complex B e (Eq. 2), length k."""
+    lib = load()
+    B = _z(B)
+    v = np.zeros(B.shape[0], dtype=np.complex128)
+    lib.oracle_zencode_row(B.shape[0], B.shape[1], _zp(B), max(B.shape[0], 1), _zp(v))
+    return v
+
+
+def zreplay(A, B, cfg: ReplayConfig, C0=None, alpha=1.0, beta=0.0, injections=None, tiles=None,
+            ev_cap=1 << 16) -> ReplayResult:
+    """Replay the online complex FT-GEMM on the CPU in complex binary64: complex
+    encodings, products and reference checksums; the real and the imaginary
+    part of every residual are checked, located and corrected on their own
+    (injections and events carry the component in ``comp``); the bound takes
+    2K' products per component and complex 2-norms.  Default u: binary64."""
+    lib = load()
+    A = _z(A)
+    B = _z(B)
+    m, k = A.shape
+    n = B.shape[1]
+    C = np.zeros((m, n), dtype=np.complex128, order="F")
+    al, be = complex(alpha), complex(beta)
+    if be != 0 and C0 is None:
+        raise ValueError("beta != 0 needs C0")
+    C0a = _z(C0) if C0 is not None else np.zeros((1, 1), dtype=np.complex128, order="F")
+    c = _Cfg(m=m, n=n, k=k, mc=cfg.mc, nc=cfg.nc, ku=cfg.ku, g=cfg.g, alpha=al.real, beta=be.real, u=cfg.u,
+             c=cfg.c, ft_level=cfg.ft_level, pad_=0)
+    inj = np.ascontiguousarray(injections if injections is not None else np.zeros(0, INJ_DTYPE), dtype=INJ_DTYPE)
+    cls = np.zeros(len(inj), dtype=CLS_DTYPE)
+    sel = None
+    if tiles is not None:
+        sel = np.ascontiguousarray(np.unique(np.asarray(tiles, dtype=np.int64).reshape(-1, 2), axis=0))
+    ev = np.zeros(ev_cap, dtype=EV_DTYPE)
+    total = lib.oracle_zftgemm_replay(
+        ctypes.byref(c), al.imag, be.imag, _zp(A), max(m, 1), _zp(B), max(k, 1), _zp(C0a), max(C0a.shape[0], 1),
+        _zp(C), max(m, 1), inj.ctypes.data if len(inj) else None, len(inj),
+        sel.ctypes.data if sel is not None else None, 0 if sel is None else len(sel),
+        cls.ctypes.data if len(inj) else None, ev.ctypes.data, ev_cap)
+    if total < 0:
+        raise ValueError(f"oracle_zftgemm_replay: invalid argument ({total})")
     return ReplayResult(C=C, events=ev[:min(total, ev_cap)].copy(), classes=cls, n_events=int(total))

@@ -186,6 +186,8 @@ struct CheckLds {
     int fslot[kMaxFaultsPerTile];
     int nf;
     int tainted;            // a check left the tile possibly wrong (cleared at tile start)
+    int nonfinite;          // check tiles already reported for non-finite operands, one bit
+                            // per check tile (bit 0: the compute tile; cleared at tile start)
 };
 
 // Extra LDS of the wavefront-tile check: per wave, the flag census of each
@@ -289,7 +291,7 @@ __device__ __forceinline__ void inject(Acc<G>& acc, CheckLds<G>& s, const Launch
                 }
                 L.old_v = oldv; L.new_v = newv;
                 L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
-                L.pad0_ = L.pad1_ = 0.f;
+                L.delta = (double)newv - (double)oldv;
                 a.fault_log[slot] = L;
             }
         }
@@ -351,6 +353,22 @@ __device__ __forceinline__ void tile_sums(const Acc<G>& acc, CheckLds<G>& s, con
     }
 }
 
+// Event of a check tile whose operands hold Inf or NaN (its norm sums are not
+// finite, so are its bound and references): logged once per check tile, by one
+// thread, at the first check that sees it; nothing is located or corrected.
+__device__ __forceinline__ void log_nonfinite(const LaunchArgs& a, int tile_m, int tile_n, int t) {
+    const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
+    atomicAdd(&a.counters[CNT_NONFINITE], 1u);
+    if ((int)e < a.event_cap) {
+        ftgemm_event_t E;
+        E.problem = a.problem; E.tile_m = tile_m; E.tile_n = tile_n; E.kstep = t;
+        E.row = -1; E.col = -1; E.kind = FTGEMM_EV_NONFINITE; E.n_rows = 0; E.n_cols = 0; E.pad_ = 0;
+        E.value_before = E.value_after = 0.f;
+        E.r_row = E.r_col = E.tau_row = E.tau_col = 0.f;
+        a.events[e] = E;
+    }
+}
+
 template <class G, int FT, bool INJ>
 __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
                       float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
@@ -370,10 +388,13 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
     float sa = 0.f, sb = 0.f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) { sa += s.nsum[0][w]; sb += s.nsum[1][w]; }
+    // An Inf or NaN operand in the k prefix makes the norm sums (uniform
+    // values) non-finite: nothing is flagged and the tile is reported once.
+    const bool finite = __builtin_amdgcn_readfirstlane((__builtin_isfinite(sa) && __builtin_isfinite(sb)) ? 1 : 0) != 0;
     const float base = a.tol_c * 2.0f * kUnitRoundoff;
     float rres = 0.f, cres = 0.f, taur = 0.f, tauc = 0.f;
     bool rf = false, cf = false;
-    if (th.my_row >= 0 && th.my_row < th.mI) {
+    if (finite && th.my_row >= 0 && th.my_row < th.mI) {
         float x = 0.f;
 #pragma unroll
         for (int w = 0; w < WN; ++w) x += s.rowpart[w][th.my_row];
@@ -381,7 +402,7 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         taur = base * (float)(kp + th.nJ + 1) * na * sb;
         rf = !(fabsf(rres) <= taur);
     }
-    if (th.my_col >= 0 && th.my_col < th.nJ) {
+    if (finite && th.my_col >= 0 && th.my_col < th.nJ) {
         float x = 0.f;
 #pragma unroll
         for (int w = 0; w < WM; ++w) x += s.colpart[w][th.my_col];
@@ -407,6 +428,13 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         s.census[th.wave][1] = fr_w;
         s.census[th.wave][2] = __popcll(cb);
         s.census[th.wave][3] = fc_w;
+    }
+    if (th.tid == 0) {
+        atomicAdd(&a.counters[CNT_CHECKS], 1u);
+        if (!finite && !(s.nonfinite & 1)) {
+            s.nonfinite |= 1;
+            log_nonfinite(a, th.tm, th.tn, t);
+        }
     }
     if constexpr (INJ) {   // complete the fault log entries this check is the first to see
         for (int q = flogged; q < fnext; ++q) {
@@ -645,10 +673,22 @@ __device__ void check_wave(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a,
     // so only the flag bits stay in registers
     const float base = a.tol_c * 2.0f * kUnitRoundoff;
     const int mine = row_role ? th.my_row : th.my_col;
+    const int line_tile = row_role ? mine / TM : mine / TN;   // own wave row / column index of the owner's line
     const bool in_range = row_role ? (th.my_row >= 0 && th.my_row < th.mI) : (th.my_col >= 0 && th.my_col < th.nJ);
+    // Check tile (r, c) whose row or column norm sums are not finite (an Inf
+    // or NaN operand in the k prefix): reported once, not decided on.
+    auto finite_tile = [&](int r, int c) -> bool {
+        float x = 0.f, y = 0.f;
+#pragma unroll
+        for (int w = 0; w < WPM; ++w) x += s.nsum[0][r * WPM + w];
+#pragma unroll
+        for (int w = 0; w < WPN; ++w) y += s.nsum[0][RW + c * WPN + w];
+        return __builtin_isfinite(x) && __builtin_isfinite(y);
+    };
     auto residual = [&](int q, float& res, float& tau) -> bool {
         const int ext = row_role ? th.nJ - q * TN : th.mI - q * TM;   // valid extent of the crossed tile
         if (!(q < cnt && in_range && ext > 0)) { res = tau = 0.f; return false; }
+        if (!(row_role ? finite_tile(line_tile, q) : finite_tile(q, line_tile))) { res = tau = 0.f; return false; }
         float other_r = 0.f, other_c = 0.f;   // sums of the other side's norms over the crossed tile
 #pragma unroll
         for (int w = 0; w < WPN; ++w) other_r += s.nsum[0][RW + q * WPN + w];
@@ -675,6 +715,15 @@ __device__ void check_wave(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a,
         if (lane == 0) { s.wcen[wave][q][0] = __popcll(b); s.wcen[wave][q][1] = first; }
     }
     if (lane == 0) s.wany[wave] = any ? 1 : 0;
+    // the wave's own check tile (wm, wn), if it holds part of C: counted, and
+    // reported once if its operands are not finite
+    if (lane == 0 && wm * TM < th.mI && wn * TN < th.nJ) {
+        atomicAdd(&a.counters[CNT_CHECKS], 1u);
+        if (!finite_tile(wm, wn) && !(s.nonfinite & (1 << wave))) {
+            atomicOr(&s.nonfinite, 1 << wave);
+            log_nonfinite(a, th.tm * WM + wm, th.tn * WN + wn, t);
+        }
+    }
     if constexpr (INJ) {   // complete the fault log entries this check is the first to see
         for (int q = flogged; q < fnext; ++q) {
             const int slot = s.fslot[q];
@@ -717,7 +766,6 @@ __device__ void check_wave(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a,
     // their values; flagged checksums of tiles that are not corrected are
     // re-based on the accumulator (online level)
     const bool online = (FT == 2) || a.ft_level == 2;
-    const int line_tile = row_role ? mine / TM : mine / TN;   // own wave row / column index of the owner's line
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         if (flags & (1u << q)) {

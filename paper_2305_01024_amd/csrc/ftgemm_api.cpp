@@ -33,6 +33,9 @@ struct ftgemm_ctx {
     // workspace of ftgemm_run_nonfused
     float* d_nf = nullptr;
     int64_t nf_cap = 0;
+    // workspace of ftgemm_run_z64 (doubles)
+    double* d_z = nullptr;
+    int64_t z_cap = 0;
     // configurations picked by ftgemm_tune, per (m, n, k, ft_level)
     std::vector<ftgemm_tuned_t> tuned;
     // batched plan of the last ftgemm_batched call
@@ -45,7 +48,6 @@ struct ftgemm_ctx {
     int bitems_cap = 0;
     int n_items = 0;
     int grid = 0;
-    uint64_t plan_checks_per_level[3] = {0, 0, 0};
     // cost model of the batched tile variants: multiply-adds per second
     double batch_rate[kBatchVariants] = {4.0e13, 2.0e13, 1.6e14};
 };
@@ -80,11 +82,11 @@ bool wants_recompute(int ft_level) { return (ft_level & FTGEMM_FT_RECOMPUTE) != 
 
 int variant_count(int dtype) {
     return dtype == FTGEMM_BF16 ? bf16_variant_count() : dtype == FTGEMM_F8E4M3 ? fp8_variant_count()
-                           : dtype == FTGEMM_F64 ? fp64_variant_count() : fp32_variant_count();
+           : (dtype == FTGEMM_F64 || dtype == FTGEMM_C64) ? fp64_variant_count() : fp32_variant_count();
 }
 Variant variant_at(int dtype, int v) {
     return dtype == FTGEMM_BF16 ? bf16_variant(v) : dtype == FTGEMM_F8E4M3 ? fp8_variant(v)
-                           : dtype == FTGEMM_F64 ? fp64_variant(v) : fp32_variant(v);
+           : (dtype == FTGEMM_F64 || dtype == FTGEMM_C64) ? fp64_variant(v) : fp32_variant(v);
 }
 // A check shape of 0 stands for the compute tile's.
 ftgemm_config_t normalized(ftgemm_config_t c) {
@@ -96,12 +98,14 @@ int find_variant(int dtype, const ftgemm_config_t& c0) {
     const ftgemm_config_t c = normalized(c0);
     return dtype == FTGEMM_BF16     ? bf16_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
            : dtype == FTGEMM_F8E4M3 ? fp8_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
-           : dtype == FTGEMM_F64    ? fp64_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
+           : (dtype == FTGEMM_F64 || dtype == FTGEMM_C64)
+                                    ? fp64_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n)
                                     : fp32_find_variant(c.m_tile, c.n_tile, c.k_step, c.check_m, c.check_n);
 }
 bool compute_tile_check(const Variant& x) { return x.check_m == x.m_tile && x.check_n == x.n_tile; }
 bool dtype_supported(int dtype) {
-    return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3 || dtype == FTGEMM_F64;
+    return dtype == FTGEMM_F32 || dtype == FTGEMM_BF16 || dtype == FTGEMM_F8E4M3 || dtype == FTGEMM_F64 ||
+           dtype == FTGEMM_C64;
 }
 
 // Modelled time of an FP32 variant on an m x n output (the k extent is common
@@ -229,7 +233,6 @@ int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
     std::vector<ftgemm_config_t> cfgs((size_t)count, ftgemm_config_t{0, 0, 0, 0, 0, 0});
     struct Work { double cost; BatchItem item; };
     std::vector<Work> work;
-    uint64_t checks[3] = {0, 0, 0};
     for (int p = 0; p < count; ++p) {
         const ftgemm_problem_t& q = probs[p];
         BatchProblem& d = bp[(size_t)p];
@@ -264,9 +267,6 @@ int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
             cfgs[(size_t)p] = {x.m_tile, x.n_tile, x.k_step, d.check_interval, x.check_m, x.check_n};
             const int64_t nk = (q.k + x.k_step - 1) / x.k_step;
             per_tile = (double)bm * bn * (double)(nk * x.k_step) / h->batch_rate[d.variant];
-            const int64_t tiles = ((q.m + bm - 1) / bm) * ((q.n + bn - 1) / bn);
-            checks[2] += (uint64_t)(tiles * ((nk + d.check_interval - 1) / d.check_interval));
-            checks[1] += (uint64_t)tiles;
         }
         d.ntm = (int32_t)((q.m + bm - 1) / bm);
         const int64_t ntn = (q.n + bn - 1) / bn;
@@ -283,9 +283,6 @@ int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
         FT_HIP(hipMemcpy(h->d_bitems, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
     h->n_items = (int)items.size();
     h->grid = std::max(1, std::min(h->n_items, batch_resident_blocks(h->device)));
-    h->plan_checks_per_level[0] = 0;
-    h->plan_checks_per_level[1] = checks[1];
-    h->plan_checks_per_level[2] = checks[2];
     h->plan_probs.assign(probs, probs + count);
     h->plan_cfg = cfgs;
     h->plan_valid = true;
@@ -297,29 +294,168 @@ bool same_plan(const ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
            (count == 0 || std::memcmp(h->plan_probs.data(), probs, sizeof(ftgemm_problem_t) * (size_t)count) == 0);
 }
 
-// Counters and events of the last launch into the report.
-int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, uint64_t checks, bool recompute = false) {
+// Counters and events of the last launch into the report.  Every count,
+// `checks` included, is taken on the device.
+int fill_report(const RunWorkspace& ws, hipStream_t stream, ftgemm_report_t* report, bool recompute = false) {
     FT_HIP(hipStreamSynchronize(stream));
     uint32_t cnt[CNT_N];
-    FT_HIP(hipMemcpy(cnt, h->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
-    report->checks = checks;
+    FT_HIP(hipMemcpy(cnt, ws.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    report->checks = cnt[CNT_CHECKS];
     report->detected = cnt[CNT_DETECTED];
     report->corrected = cnt[CNT_CORRECTED];
     report->uncorrectable = cnt[CNT_UNCORRECTABLE];
     report->checksum_only = cnt[CNT_CHECKSUM_ONLY];
+    report->nonfinite_input = cnt[CNT_NONFINITE];
     report->recomputed = cnt[CNT_RECOMPUTED];
     report->recompute_failed = cnt[CNT_RECOMPUTE_FAILED];
-    const uint32_t logged = std::min<uint32_t>(cnt[CNT_EVENTS], (uint32_t)h->event_cap);
+    const uint32_t logged = std::min<uint32_t>(cnt[CNT_EVENTS], (uint32_t)ws.event_cap);
     const uint32_t copy = report->events ? std::min<uint32_t>(logged, report->cap_events) : 0;
     if (copy > 0)
-        FT_HIP(hipMemcpy(report->events, h->d_events, sizeof(ftgemm_event_t) * copy, hipMemcpyDeviceToHost));
+        FT_HIP(hipMemcpy(report->events, ws.events, sizeof(ftgemm_event_t) * copy, hipMemcpyDeviceToHost));
     report->n_events = copy;
     if (cnt[CNT_EVENTS] > copy && report->events) return FTGEMM_LOG_OVERFLOW;
-    if (recompute) return report->recompute_failed > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
-    return report->uncorrectable > 0 ? FTGEMM_UNCORRECTABLE : FTGEMM_OK;
+    if (recompute ? report->recompute_failed > 0 : report->uncorrectable > 0) return FTGEMM_UNCORRECTABLE;
+    return report->nonfinite_input > 0 ? FTGEMM_NONFINITE_INPUT : FTGEMM_OK;
+}
+
+// The device memory of a handle as a run's workspace.
+RunWorkspace workspace_of(const ftgemm_ctx* h) {
+    RunWorkspace ws{};
+    ws.counters = h->d_counters;
+    ws.events = h->d_events;
+    ws.event_cap = h->event_cap;
+    ws.faults = h->n_faults > 0 ? h->d_faults : nullptr;
+    ws.n_faults = h->n_faults;
+    ws.fault_log = h->d_flog;
+    ws.fault_log_cap = h->flog_cap;
+    ws.retry = h->d_retry;
+    ws.retry_tiles = h->d_retry_tiles;
+    ws.retry_cap = h->retry_cap;
+    return ws;
+}
+int fill_report(ftgemm_ctx* h, hipStream_t stream, ftgemm_report_t* report, bool recompute = false) {
+    return fill_report(workspace_of(h), stream, report, recompute);
+}
+
+// Zero the report's outputs (the caller's events and cap_events stay).
+void reset_report(ftgemm_report_t* report) {
+    if (!report) return;
+    report->checks = report->detected = report->corrected = 0;
+    report->uncorrectable = report->checksum_only = report->nonfinite_input = 0;
+    report->n_events = 0;
+    report->bad_arg = 0;
+    report->tol_used = 0.f;
+    report->bad_problem = -1;
+    report->recomputed = report->recompute_failed = 0;
+    std::memset(&report->config, 0, sizeof(report->config));
 }
 
 }  // namespace
+
+namespace ftgemm_impl {
+
+// Body of ftgemm_run and ftgemm_run_noalloc: argument checks, BLAS quick
+// returns, configuration, the launches and the report, on the workspace `ws`
+// and the current device.  `h` (may be null) supplies a forced or tuned
+// configuration and grows its own recompute queue; without a handle the
+// queue must already hold every tile (FTGEMM_NO_MEMORY otherwise).
+int run_common(ftgemm_ctx* h, int dtype, float scale, RunWorkspace ws, int64_t m, int64_t n, int64_t k,
+               float alpha, const void* A, int64_t lda, const void* B, int64_t ldb, float beta, float* C,
+               int64_t ldc, int ft_level, float tol, hipStream_t stream, ftgemm_report_t* report) {
+    int32_t bad = 0;
+    if (ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level, tol, &bad) != FTGEMM_OK) {
+        if (report) report->bad_arg = bad;
+        return FTGEMM_INVALID;
+    }
+    if (!dtype_supported(dtype) || dtype == FTGEMM_F64 || dtype == FTGEMM_C64)
+        return FTGEMM_UNSUPPORTED;   // binary64: ftgemm_run_f64, complex: ftgemm_run_z64
+    const float c = tol > 0.f ? tol : 2.0f;
+    if (report) report->tol_used = c;
+    if (m == 0 || n == 0) return FTGEMM_OK;
+    if (!C) {
+        if (report) report->bad_arg = 11;
+        return FTGEMM_INVALID;
+    }
+    if (k == 0 || alpha == 0.f) {
+        FT_HIP(launch_scale(C, ldc, (int32_t)m, (int32_t)n, beta, stream));
+        if (report) FT_HIP(hipStreamSynchronize(stream));
+        return FTGEMM_OK;
+    }
+    if (!A || !B) {
+        if (report) report->bad_arg = !A ? 6 : 8;
+        return FTGEMM_INVALID;
+    }
+
+    const bool recompute = wants_recompute(ft_level);
+    ft_level = base_level(ft_level);
+    ftgemm_config_t cfg;
+    if (h && h->forced) cfg = h->cfg;
+    else if (!(h && find_tuned(h, m, n, k, ft_level, &cfg))) select_variant(dtype, m, n, ft_level, &cfg);
+    const int variant = find_variant(dtype, cfg);
+    if (variant < 0) return FTGEMM_UNSUPPORTED;
+    const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
+    if (recompute) {
+        if (h) {
+            if (grow(&h->d_retry_tiles, &h->retry_cap, (int)ntiles) != FTGEMM_OK) return FTGEMM_NO_MEMORY;
+            ws.retry_tiles = h->d_retry_tiles;
+            ws.retry_cap = h->retry_cap;
+        } else if (ntiles > ws.retry_cap) {
+            return FTGEMM_NO_MEMORY;
+        }
+    }
+
+    const bool inject = ws.n_faults > 0;
+    if (report || inject) FT_HIP(launch_zero_u32(ws.counters, CNT_N, stream));
+
+    LaunchArgs a{};
+    a.A = static_cast<const float*>(A);
+    a.B = static_cast<const float*>(B);
+    a.C = C;
+    a.lda = lda;
+    a.ldb = ldb;
+    a.ldc = ldc;
+    a.M = (int32_t)m;
+    a.N = (int32_t)n;
+    a.K = (int32_t)k;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.scale = scale;
+    a.tol_c = c;
+    a.check_interval = ft_level == 1 ? INT32_MAX : cfg.check_interval;   // detect-only: after the last step
+    a.ft_level = ft_level;
+    a.problem = 0;
+    a.events = ws.events;
+    a.counters = ws.counters;
+    a.event_cap = ws.event_cap;
+    a.faults = inject ? ws.faults : nullptr;
+    a.n_faults = inject ? ws.n_faults : 0;
+    a.fault_log = ws.fault_log;
+    a.fault_log_cap = ws.fault_log_cap;
+    a.retry = recompute ? ws.retry : nullptr;
+    a.retry_tiles = recompute ? ws.retry_tiles : nullptr;
+    a.retry_pass = 0;
+    if (dtype == FTGEMM_BF16) FT_HIP(launch_bf16(variant, inject, a, stream));
+    else if (dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8(variant, inject, a, stream));
+    else FT_HIP(launch_fp32(variant, inject, a, stream));
+    if (recompute) {
+        // the queued tiles again, without injection; one workgroup per compute
+        // unit at most, each walking the queue
+        LaunchArgs r = a;
+        r.retry_pass = 1;
+        r.faults = nullptr;
+        r.n_faults = 0;
+        const int grid = (int)std::min<int64_t>(ntiles, kNumCUs);
+        if (dtype == FTGEMM_BF16) FT_HIP(launch_bf16_retry(variant, r, grid, stream));
+        else if (dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8_retry(variant, r, grid, stream));
+        else FT_HIP(launch_fp32_retry(variant, r, grid, stream));
+    }
+
+    if (!report) return FTGEMM_OK;
+    report->config = cfg;
+    return fill_report(ws, stream, report, recompute);
+}
+
+}  // namespace ftgemm_impl
 
 extern "C" {
 
@@ -327,6 +463,7 @@ const char* ftgemm_status_string(int s) {
     switch (s) {
         case FTGEMM_OK: return "ok";
         case FTGEMM_UNCORRECTABLE: return "uncorrectable fault pattern in at least one tile";
+        case FTGEMM_NONFINITE_INPUT: return "operands hold Inf or NaN: the tiles that read them were not checked";
         case FTGEMM_INVALID: return "invalid argument";
         case FTGEMM_UNSUPPORTED: return "unsupported dtype, level, configuration or device";
         case FTGEMM_HIP_ERROR: return "HIP runtime error";
@@ -404,6 +541,7 @@ int ftgemm_destroy(ftgemm_t h) {
         if (h->d_retry) (void)hipFree(h->d_retry);
         if (h->d_retry_tiles) (void)hipFree(h->d_retry_tiles);
         if (h->d_nf) (void)hipFree(h->d_nf);
+        if (h->d_z) (void)hipFree(h->d_z);
     }
     delete h;
     return FTGEMM_OK;
@@ -436,7 +574,7 @@ int ftgemm_set_injection(ftgemm_t h, const ftgemm_fault_t* faults, int n) {
         if (f.tile_m < 0 || f.tile_n < 0 || f.kstep < 0 || f.row < 0 || f.col < 0 || f.problem < 0)
             return FTGEMM_INVALID;
         if (f.kind != FTGEMM_FAULT_ADD && f.kind != FTGEMM_FAULT_XOR) return FTGEMM_INVALID;
-        const float top_bit = h->dtype == FTGEMM_F64 ? 63.f : 31.f;
+        const float top_bit = (h->dtype == FTGEMM_F64 || h->dtype == FTGEMM_C64) ? 63.f : 31.f;
         if (f.kind == FTGEMM_FAULT_XOR && !(f.payload >= 0.f && f.payload <= top_bit)) return FTGEMM_INVALID;
     }
     DeviceGuard g(h->device);
@@ -463,131 +601,29 @@ int ftgemm_get_injection_log(ftgemm_t h, ftgemm_fault_log_t* out, int cap, int* 
     const int applied = (int)cnt[CNT_FAULTS];
     const int copy = std::min(std::min(applied, cap), h->flog_cap);
     if (copy > 0) FT_HIP(hipMemcpy(out, h->d_flog, sizeof(ftgemm_fault_log_t) * (size_t)copy, hipMemcpyDeviceToHost));
-    if (n) *n = applied;
-    return FTGEMM_OK;
+    if (n) *n = copy;
+    return applied > copy ? FTGEMM_LOG_OVERFLOW : FTGEMM_OK;
 }
 
 int ftgemm_run(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
                const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int ft_level, float tol,
                hipStream_t stream, ftgemm_report_t* report) {
-    int32_t bad = 0;
-    if (report) {
-        report->checks = report->detected = report->corrected = 0;
-        report->uncorrectable = report->checksum_only = 0;
-        report->n_events = 0;
-        report->bad_arg = 0;
-        report->tol_used = 0.f;
-        report->bad_problem = -1;
-        report->recomputed = report->recompute_failed = 0;
-        std::memset(&report->config, 0, sizeof(report->config));
-    }
+    reset_report(report);
     if (!h) {
         if (report) report->bad_arg = 1;
         return FTGEMM_INVALID;
     }
-    if (ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level, tol, &bad) != FTGEMM_OK) {
-        if (report) report->bad_arg = bad;
-        return FTGEMM_INVALID;
-    }
-    if (!dtype_supported(h->dtype) || h->dtype == FTGEMM_F64) return FTGEMM_UNSUPPORTED;   // FP64: ftgemm_run_f64
-    const float c = tol > 0.f ? tol : 2.0f;
-    if (report) report->tol_used = c;
-    if (m == 0 || n == 0) return FTGEMM_OK;
-    if (!C) {
-        if (report) report->bad_arg = 11;
-        return FTGEMM_INVALID;
-    }
     DeviceGuard g(h->device);
-    if (k == 0 || alpha == 0.f) {
-        FT_HIP(launch_scale(C, ldc, (int32_t)m, (int32_t)n, beta, stream));
-        if (report) FT_HIP(hipStreamSynchronize(stream));
-        return FTGEMM_OK;
-    }
-    if (!A || !B) {
-        if (report) report->bad_arg = !A ? 6 : 8;
-        return FTGEMM_INVALID;
-    }
-
-    const bool recompute = wants_recompute(ft_level);
-    ft_level = base_level(ft_level);
-    ftgemm_config_t cfg;
-    if (h->forced) cfg = h->cfg;
-    else if (!find_tuned(h, m, n, k, ft_level, &cfg)) select_variant(h->dtype, m, n, ft_level, &cfg);
-    const int variant = find_variant(h->dtype, cfg);
-    if (variant < 0) return FTGEMM_UNSUPPORTED;
-    const int64_t ntiles = ((m + cfg.m_tile - 1) / cfg.m_tile) * ((n + cfg.n_tile - 1) / cfg.n_tile);
-    if (recompute && grow(&h->d_retry_tiles, &h->retry_cap, (int)ntiles) != FTGEMM_OK) return FTGEMM_NO_MEMORY;
-
-    const bool inject = h->n_faults > 0;
-    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
-
-    LaunchArgs a{};
-    a.A = static_cast<const float*>(A);
-    a.B = static_cast<const float*>(B);
-    a.C = C;
-    a.lda = lda;
-    a.ldb = ldb;
-    a.ldc = ldc;
-    a.M = (int32_t)m;
-    a.N = (int32_t)n;
-    a.K = (int32_t)k;
-    a.alpha = alpha;
-    a.beta = beta;
-    a.scale = h->dtype == FTGEMM_F32 ? 1.0f : h->scale_a * h->scale_b;
-    a.tol_c = c;
-    a.check_interval = ft_level == 1 ? INT32_MAX : cfg.check_interval;   // detect-only: after the last step
-    a.ft_level = ft_level;
-    a.problem = 0;
-    a.events = h->d_events;
-    a.counters = h->d_counters;
-    a.event_cap = h->event_cap;
-    a.faults = inject ? h->d_faults : nullptr;
-    a.n_faults = inject ? h->n_faults : 0;
-    a.fault_log = h->d_flog;
-    a.fault_log_cap = h->flog_cap;
-    a.retry = recompute ? h->d_retry : nullptr;
-    a.retry_tiles = recompute ? h->d_retry_tiles : nullptr;
-    a.retry_pass = 0;
-    if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16(variant, inject, a, stream));
-    else if (h->dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8(variant, inject, a, stream));
-    else FT_HIP(launch_fp32(variant, inject, a, stream));
-    if (recompute) {
-        // the queued tiles again, without injection; one workgroup per compute
-        // unit at most, each walking the queue
-        LaunchArgs r = a;
-        r.retry_pass = 1;
-        r.faults = nullptr;
-        r.n_faults = 0;
-        const int grid = (int)std::min<int64_t>(ntiles, kNumCUs);
-        if (h->dtype == FTGEMM_BF16) FT_HIP(launch_bf16_retry(variant, r, grid, stream));
-        else if (h->dtype == FTGEMM_F8E4M3) FT_HIP(launch_fp8_retry(variant, r, grid, stream));
-        else FT_HIP(launch_fp32_retry(variant, r, grid, stream));
-    }
-
-    if (!report) return FTGEMM_OK;
-    report->config = cfg;
-    const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
-    const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
-                           : ft_level == 1 ? 1 : 0;
-    // check tiles that hold part of C (a wavefront tile past the edge is not checked)
-    const int64_t nchk = ((m + cfg.check_m - 1) / cfg.check_m) * ((n + cfg.check_n - 1) / cfg.check_n);
-    return fill_report(h, stream, report, (uint64_t)(nchk * per_tile), recompute);
+    const float scale = h->dtype == FTGEMM_F32 ? 1.0f : h->scale_a * h->scale_b;
+    return run_common(h, h->dtype, scale, workspace_of(h), m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                      ft_level, tol, stream, report);
 }
 
 int ftgemm_run_f64(ftgemm_t h, int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int ft_level, double tol,
                    hipStream_t stream, ftgemm_report_t* report) {
     int32_t bad = 0;
-    if (report) {
-        report->checks = report->detected = report->corrected = 0;
-        report->uncorrectable = report->checksum_only = 0;
-        report->n_events = 0;
-        report->bad_arg = 0;
-        report->tol_used = 0.f;
-        report->bad_problem = -1;
-        report->recomputed = report->recompute_failed = 0;
-        std::memset(&report->config, 0, sizeof(report->config));
-    }
+    reset_report(report);
     if (!h) {
         if (report) report->bad_arg = 1;
         return FTGEMM_INVALID;
@@ -621,7 +657,7 @@ int ftgemm_run_f64(ftgemm_t h, int64_t m, int64_t n, int64_t k, double alpha, co
     if (variant < 0) return FTGEMM_UNSUPPORTED;
 
     const bool inject = h->n_faults > 0;
-    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
+    if (report || inject) FT_HIP(launch_zero_u32(h->d_counters, CNT_N, stream));
     F64Args a{};
     a.A = A;
     a.B = B;
@@ -648,27 +684,110 @@ int ftgemm_run_f64(ftgemm_t h, int64_t m, int64_t n, int64_t k, double alpha, co
     FT_HIP(launch_fp64(variant, inject, a, stream));
     if (!report) return FTGEMM_OK;
     report->config = cfg;
-    const int64_t nk = (k + cfg.k_step - 1) / cfg.k_step;
-    const int64_t per_tile = ft_level == 2 ? (nk + cfg.check_interval - 1) / cfg.check_interval
-                           : ft_level == 1 ? 1 : 0;
-    const int64_t nchk = ((m + cfg.check_m - 1) / cfg.check_m) * ((n + cfg.check_n - 1) / cfg.check_n);
-    return fill_report(h, stream, report, (uint64_t)(nchk * per_tile));
+    return fill_report(h, stream, report);
+}
+
+int ftgemm_run_z64(ftgemm_t h, int64_t m, int64_t n, int64_t k, const double* alpha, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, const double* beta, void* C, int64_t ldc, int ft_level, double tol,
+                   hipStream_t stream, ftgemm_report_t* report) {
+    int32_t bad = 0;
+    reset_report(report);
+    if (!h) {
+        if (report) report->bad_arg = 1;
+        return FTGEMM_INVALID;
+    }
+    if (ftgemm_validate(m, n, k, lda, ldb, ldc, ft_level, (float)std::min(tol, 1e31), &bad) != FTGEMM_OK) {
+        if (report) report->bad_arg = bad;
+        return FTGEMM_INVALID;
+    }
+    if (!alpha || !beta) {
+        if (report) report->bad_arg = !alpha ? 5 : 10;
+        return FTGEMM_INVALID;
+    }
+    // the real products have 2k inner indices
+    if (2 * k > INT32_MAX) {
+        if (report) report->bad_arg = 4;
+        return FTGEMM_INVALID;
+    }
+    if (h->dtype != FTGEMM_C64 || wants_recompute(ft_level)) return FTGEMM_UNSUPPORTED;
+    const float c = tol > 0.0 ? (float)tol : 2.0f;
+    if (report) report->tol_used = c;
+    if (m == 0 || n == 0) return FTGEMM_OK;
+    if (!C) {
+        if (report) report->bad_arg = 11;
+        return FTGEMM_INVALID;
+    }
+    DeviceGuard g(h->device);
+    double* Cz = static_cast<double*>(C);
+    if (k == 0 || (alpha[0] == 0.0 && alpha[1] == 0.0)) {
+        FT_HIP(launch_zscale(Cz, ldc, (int32_t)m, (int32_t)n, beta, stream));
+        if (report) FT_HIP(hipStreamSynchronize(stream));
+        return FTGEMM_OK;
+    }
+    if (!A || !B) {
+        if (report) report->bad_arg = !A ? 6 : 8;
+        return FTGEMM_INVALID;
+    }
+    ftgemm_config_t cfg;
+    if (h->forced) cfg = h->cfg;
+    else select_variant(FTGEMM_C64, m, n, ft_level, &cfg);
+    const int variant = find_variant(FTGEMM_C64, cfg);
+    if (variant < 0) return FTGEMM_UNSUPPORTED;
+
+    // workspace: A', A'' (m x 2k each), then the real and imaginary accumulators (m x n each)
+    const int64_t need = 4 * m * k + 2 * m * n;
+    if (need > h->z_cap) {
+        if (h->d_z) (void)hipFree(h->d_z);
+        h->d_z = nullptr;
+        h->z_cap = 0;
+        if (hipMalloc(&h->d_z, sizeof(double) * (size_t)need) != hipSuccess) return FTGEMM_NO_MEMORY;
+        h->z_cap = need;
+    }
+    double* Ap = h->d_z;
+    double* App = Ap + 2 * m * k;
+    double* Pr = App + 2 * m * k;
+    double* Pi = Pr + m * n;
+    FT_HIP(launch_zrepack(static_cast<const double*>(A), lda, (int32_t)m, (int32_t)k, Ap, App, stream));
+
+    const bool inject = h->n_faults > 0;
+    if (report || inject) FT_HIP(launch_zero_u32(h->d_counters, CNT_N, stream));
+    F64Args a{};
+    a.B = static_cast<const double*>(B);   // B' = B's (re, im) storage as a real 2k x n matrix
+    a.lda = m;
+    a.ldb = 2 * ldb;
+    a.ldc = m;
+    a.M = (int32_t)m;
+    a.N = (int32_t)n;
+    a.K = (int32_t)(2 * k);
+    a.alpha = 1.0;
+    a.beta = 0.0;
+    a.tol_c = c;
+    a.check_interval = ft_level == 1 ? INT32_MAX : cfg.check_interval;   // detect-only: after the last step
+    a.ft_level = ft_level;
+    a.events = h->d_events;
+    a.counters = h->d_counters;
+    a.event_cap = h->event_cap;
+    a.faults = inject ? h->d_faults : nullptr;
+    a.n_faults = inject ? h->n_faults : 0;
+    a.fault_log = h->d_flog;
+    a.fault_log_cap = h->flog_cap;
+    for (int comp = 0; comp < 2; ++comp) {   // real part, then imaginary part
+        a.A = comp == 0 ? Ap : App;
+        a.C = comp == 0 ? Pr : Pi;
+        a.problem = comp;
+        FT_HIP(launch_fp64(variant, inject, a, stream));
+    }
+    FT_HIP(launch_zepilogue(Cz, ldc, (int32_t)m, (int32_t)n, Pr, Pi, alpha, beta, stream));
+    if (!report) return FTGEMM_OK;
+    report->config = cfg;
+    return fill_report(h, stream, report);
 }
 
 int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
                         const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int check_k, float tol,
                         hipStream_t stream, ftgemm_report_t* report) {
     int32_t bad = 0;
-    if (report) {
-        report->checks = report->detected = report->corrected = 0;
-        report->uncorrectable = report->checksum_only = 0;
-        report->n_events = 0;
-        report->bad_arg = 0;
-        report->tol_used = 0.f;
-        report->bad_problem = -1;
-        report->recomputed = report->recompute_failed = 0;
-        std::memset(&report->config, 0, sizeof(report->config));
-    }
+    reset_report(report);
     if (!h) bad = 1;
     else if (ftgemm_validate(m, n, k, lda, ldb, ldc, FTGEMM_FT_CORRECT, tol, &bad) != FTGEMM_OK) {}
     else if (check_k < 0) bad = 13;
@@ -699,7 +818,7 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
     const int64_t ck = check_k > 0 ? check_k : 256;
     const int64_t nchunks = (k + ck - 1) / ck;
     // workspace: W [ntm][k], V [ntn][k], R [ntn][m], S [ntm][n], na2 [m], nb2 [n]
-    const int64_t need = ntm * k + ntn * k + ntn * m + ntm * n + m + n;
+    const int64_t need = ntm * k + ntn * k + ntn * m + ntm * n + m + n + ntm * ntn;
     if (need > h->nf_cap) {
         if (h->d_nf) (void)hipFree(h->d_nf);
         h->d_nf = nullptr;
@@ -724,6 +843,7 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
     nf.S = nf.R + ntn * m;
     nf.na2 = nf.S + ntm * n;
     nf.nb2 = nf.na2 + m;
+    nf.tile_flag = reinterpret_cast<unsigned*>(nf.nb2 + n);
     nf.events = h->d_events;
     nf.event_cap = h->event_cap;
     nf.counters = h->d_counters;
@@ -733,7 +853,7 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
     nf.fault_log = h->d_flog;
     nf.fault_log_cap = h->flog_cap;
     if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
-    FT_HIP(hipMemsetAsync(nf.R, 0, sizeof(float) * (size_t)(ntn * m + ntm * n + m + n), stream));
+    FT_HIP(hipMemsetAsync(nf.R, 0, sizeof(float) * (size_t)(ntn * m + ntm * n + m + n + ntm * ntn), stream));
     FT_HIP(launch_nonfused_encode(nf, stream));
 
     // the plain kernel for the chunk shape: a configuration tuned for (m, n, chunk) at
@@ -770,21 +890,12 @@ int ftgemm_run_nonfused(ftgemm_t h, int64_t m, int64_t n, int64_t k, float alpha
     }
     if (!report) return FTGEMM_OK;
     report->config = ftgemm_config_t{(int32_t)T, (int32_t)T, (int32_t)ck, 1, (int32_t)T, (int32_t)T};
-    return fill_report(h, stream, report, (uint64_t)(ntm * ntn * nchunks));
+    return fill_report(h, stream, report);
 }
 
 int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_level, float tol,
                    hipStream_t stream, ftgemm_report_t* report) {
-    if (report) {
-        report->checks = report->detected = report->corrected = 0;
-        report->uncorrectable = report->checksum_only = 0;
-        report->n_events = 0;
-        report->bad_arg = 0;
-        report->tol_used = 0.f;
-        report->bad_problem = -1;
-        report->recomputed = report->recompute_failed = 0;
-        std::memset(&report->config, 0, sizeof(report->config));
-    }
+    reset_report(report);
     int bad = 0;
     if (!h) bad = 1;
     else if (count < 0 || (count > 0 && !probs)) bad = 2;
@@ -824,7 +935,7 @@ int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_
             return st;
         }
     }
-    if (report || inject) FT_HIP(hipMemsetAsync(h->d_counters, 0, sizeof(uint32_t) * CNT_N, stream));
+    if (report || inject) FT_HIP(launch_zero_u32(h->d_counters, CNT_N, stream));
     BatchArgs b{};
     b.probs = h->d_bprobs;
     b.items = h->d_bitems;
@@ -840,7 +951,7 @@ int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_
     b.fault_log = h->d_flog;
     FT_HIP(launch_batched(b, inject, h->grid, stream));
     if (!report) return FTGEMM_OK;
-    return fill_report(h, stream, report, h->plan_checks_per_level[ft_level]);
+    return fill_report(h, stream, report);
 }
 
 int ftgemm_batched_config(ftgemm_t h, int p, ftgemm_config_t* config) {
@@ -878,7 +989,7 @@ int ftgemm_tune(ftgemm_t h, int64_t m, int64_t n, int64_t k, int ft_level, int m
                               ft_level, 0.f, nullptr) != FTGEMM_OK || m == 0 || n == 0 || k == 0 ||
         max_k_between_checks < 0)
         return FTGEMM_INVALID;
-    if (!dtype_supported(h->dtype) || h->dtype == FTGEMM_F64) return FTGEMM_UNSUPPORTED;
+    if (!dtype_supported(h->dtype) || h->dtype == FTGEMM_F64 || h->dtype == FTGEMM_C64) return FTGEMM_UNSUPPORTED;
     ft_level = base_level(ft_level);   // configurations are kept per level; recompute does not change them
     const int kmax = max_k_between_checks > 0 ? max_k_between_checks : 256;
     const size_t esz = h->dtype == FTGEMM_F32 ? 4 : h->dtype == FTGEMM_BF16 ? 2 : 1;

@@ -1,5 +1,7 @@
 // ftgemm_fp32.hip -- kernel entry points and variant table of the FP32 kernels
 // (the tile computation is in ftgemm_fp32.hpp).
+#include <algorithm>
+
 #include "ftgemm_fp32.hpp"
 
 namespace ftgemm_impl {
@@ -24,6 +26,10 @@ __global__ __launch_bounds__(64 * WM * WN) void ftgemm_f32_retry_kernel(LaunchAr
     __shared__ f32::Smem<BM, BN, BK, WM, WN, WAVE> sm;
     const int ntm = (a.M + BM - 1) / BM;
     abft::retry_queue(a, ntm, [&](int tm, int tn) { f32::tile<BM, BN, BK, WM, WN, FT, false, WAVE>(a, tm, tn, sm); });
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) p[x] = 0u;
 }
 
 __global__ void scale_kernel(float* C, int64_t ldc, int32_t M, int32_t N, float beta) {
@@ -125,6 +131,12 @@ hipError_t launch_fp32_retry(int idx, const LaunchArgs& a, int grid, hipStream_t
         case 5: return launch_shape_retry<128, 128, 32, 2, 2, true>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)std::max(1, std::min(64, (n + 255) / 256))), dim3(256), 0, s,
+                       p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t s) {

@@ -19,7 +19,9 @@ enum Counter : int {
     CNT_FAULTS = 5,        // faults applied by the injection hook
     CNT_RECOMPUTED = 6,    // tiles recomputed by the retry launch
     CNT_RECOMPUTE_FAILED = 7,  // retried tiles whose own checks still flagged a fault
-    CNT_N = 8
+    CNT_CHECKS = 8,        // checks performed (one per check tile and check step)
+    CNT_NONFINITE = 9,     // check tiles reported once for non-finite operands
+    CNT_N = 10
 };
 
 // Maximum fault sites one tile may hold in the injection build.
@@ -120,6 +122,16 @@ int fp64_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check
 hipError_t launch_fp64(int idx, bool inject, const F64Args& a, hipStream_t stream);
 hipError_t launch_scale64(double* C, int64_t ldc, int32_t M, int32_t N, double beta, hipStream_t stream);
 
+// ---- double complex through two binary64 products (ftgemm_complex.hip) ----
+// A (m x k complex) -> A' = (Re A, -Im A) and A'' = (Im A, Re A) interleaved
+// along k (m x 2k real, leading dimension m)
+hipError_t launch_zrepack(const double* A, int64_t lda, int32_t M, int32_t K, double* Ap, double* App,
+                          hipStream_t stream);
+// C = alpha (Pr + i Pi) + beta C, alpha / beta host (re, im) pairs
+hipError_t launch_zepilogue(double* C, int64_t ldc, int32_t M, int32_t N, const double* Pr, const double* Pi,
+                            const double* alpha, const double* beta, hipStream_t stream);
+hipError_t launch_zscale(double* C, int64_t ldc, int32_t M, int32_t N, const double* beta, hipStream_t stream);
+
 // ---- batched persistent launch ----
 // Device descriptor of one problem of a batched call.
 struct BatchProblem {
@@ -179,6 +191,7 @@ struct NonFusedArgs {
     float* S;      // [ntm][N]  column references
     float* na2;    // [M]       prefix ||a_i||^2
     float* nb2;    // [N]       prefix ||b_j||^2
+    unsigned* tile_flag;   // [ntm * ntn] tile reported for non-finite operands
     ftgemm_event_t* events;
     int32_t event_cap;
     uint32_t* counters;
@@ -193,5 +206,31 @@ hipError_t launch_nonfused_chunk(const NonFusedArgs& n, int c, int k0, int k1, h
 
 // C = beta * C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale(float* C, int64_t ldc, int32_t M, int32_t N, float beta, hipStream_t stream);
+// p[0 .. n) = 0 by a kernel (no memset node, so it replays correctly inside a HIP graph).
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t stream);
+
+// Device memory a run uses besides its operands: the counters, the event log,
+// the fault sites and applied-fault log of the injection build, and the
+// recompute queue (retry[0..1] zero between calls; retry_tiles holds
+// retry_cap tile indices).  A handle owns one; ftgemm_run_noalloc uses a
+// static one.
+struct RunWorkspace {
+    uint32_t* counters;
+    ftgemm_event_t* events;
+    int32_t event_cap;
+    const ftgemm_fault_t* faults;
+    int32_t n_faults;
+    ftgemm_fault_log_t* fault_log;
+    int32_t fault_log_cap;
+    uint32_t* retry;
+    int32_t* retry_tiles;
+    int64_t retry_cap;
+};
+
+// Body of ftgemm_run and ftgemm_run_noalloc on the current device (defined in
+// ftgemm_api.cpp).  `h` may be null.
+int run_common(ftgemm_ctx* h, int dtype, float scale, RunWorkspace ws, int64_t m, int64_t n, int64_t k,
+               float alpha, const void* A, int64_t lda, const void* B, int64_t ldb, float beta, float* C,
+               int64_t ldc, int ft_level, float tol, hipStream_t stream, ftgemm_report_t* report);
 
 }  // namespace ftgemm_impl

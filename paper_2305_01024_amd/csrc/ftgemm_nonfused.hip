@@ -134,7 +134,8 @@ __global__ void nf_inject(float* C, int64_t ldc, int M, int N, const ftgemm_faul
         ftgemm_fault_log_t L;
         L.problem = 0; L.tile_m = f.tile_m; L.tile_n = f.tile_n; L.kstep = c; L.row = f.row; L.col = f.col;
         L.kind = f.kind; L.check_step = c; L.old_v = old; L.new_v = nv;
-        L.r_row = L.r_col = L.tau_row = L.tau_col = L.pad0_ = L.pad1_ = 0.f;
+        L.r_row = L.r_col = L.tau_row = L.tau_col = 0.f;
+        L.delta = (double)nv - (double)old;
         flog[slot] = L;
     }
 }
@@ -152,9 +153,13 @@ struct CheckShared {
 // reduction per column) of C against R and S with the FP32 roundoff threshold of the
 // fused kernels; one row and one column flagged: C[i][j] = R_i - sum_{j' != j} C[i][j'];
 // other patterns re-base the flagged checksums and are logged.  256 threads.
+// A tile whose norm sums are not finite (an Inf or NaN operand in the k
+// prefix) is reported once (tile_flag remembers it across chunks) and not
+// decided on.
 __global__ __launch_bounds__(256) void nf_check(float* C, int64_t ldc, int M, int N, int ntm, int kp, int c,
                                                 float tol_c, float* R, float* S, const float* na2, const float* nb2,
-                                                ftgemm_event_t* events, int event_cap, uint32_t* counters) {
+                                                unsigned* tile_flag, ftgemm_event_t* events, int event_cap,
+                                                uint32_t* counters) {
     __shared__ CheckShared sh;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
@@ -184,6 +189,23 @@ __global__ __launch_bounds__(256) void nf_check(float* C, int64_t ldc, int M, in
     __syncthreads();
     const float sa = sh.nsum[0][0] + sh.nsum[0][1] + sh.nsum[0][2] + sh.nsum[0][3];
     const float sb = sh.nsum[1][0] + sh.nsum[1][1] + sh.nsum[1][2] + sh.nsum[1][3];
+    if (t == 0) atomicAdd(&counters[CNT_CHECKS], 1u);
+    if (!(__builtin_isfinite(sa) && __builtin_isfinite(sb))) {
+        if (t == 0 && tile_flag[blockIdx.x] == 0u) {
+            tile_flag[blockIdx.x] = 1u;
+            const unsigned e = atomicAdd(&counters[CNT_EVENTS], 1u);
+            atomicAdd(&counters[CNT_NONFINITE], 1u);
+            if ((int)e < event_cap) {
+                ftgemm_event_t E;
+                E.problem = 0; E.tile_m = tm; E.tile_n = tn; E.kstep = c; E.row = -1; E.col = -1;
+                E.kind = FTGEMM_EV_NONFINITE; E.n_rows = 0; E.n_cols = 0; E.pad_ = 0;
+                E.value_before = E.value_after = 0.f;
+                E.r_row = E.r_col = E.tau_row = E.tau_col = 0.f;
+                events[e] = E;
+            }
+        }
+        return;
+    }
     const float base = tol_c * 2.0f * abft::kUnitRoundoff;
     bool rf = false, cf = false;
     float rres = 0.f, rtau = 0.f, cres = 0.f, ctau = 0.f, rref = 0.f;
@@ -281,7 +303,7 @@ hipError_t launch_nonfused_chunk(const NonFusedArgs& n, int c, int k0, int k1, h
         hipLaunchKernelGGL(nf_inject, dim3((unsigned)((n.n_faults + 255) / 256)), dim3(256), 0, s, n.C, n.ldc, n.M,
                            n.N, n.faults, n.n_faults, c, n.fault_log, n.fault_log_cap, n.counters);
     hipLaunchKernelGGL(nf_check, dim3((unsigned)(ntm * ntn)), dim3(256), 0, s, n.C, n.ldc, n.M, n.N, ntm, k1, c,
-                       n.tol_c, n.R, n.S, n.na2, n.nb2, n.events, n.event_cap, n.counters);
+                       n.tol_c, n.R, n.S, n.na2, n.nb2, n.tile_flag, n.events, n.event_cap, n.counters);
     return hipGetLastError();
 }
 

@@ -16,11 +16,12 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libftgemm.so")
 
-F32, BF16, F8E4M3, F64 = 0, 1, 2, 3
+F32, BF16, F8E4M3, F64, C64 = 0, 1, 2, 3, 4
 FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
 FT_RECOMPUTE = 0x10   # OR-ed into FT_DETECT or FT_CORRECT: recompute the tiles that end possibly wrong
-OK, UNCORRECTABLE, INVALID, UNSUPPORTED, HIP_ERROR, NO_MEMORY, LOG_OVERFLOW = 0, 1, -1, -2, -3, -4, -5
-EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED = 1, 2, 3, 4, 5
+OK, UNCORRECTABLE, NONFINITE_INPUT = 0, 1, 2
+INVALID, UNSUPPORTED, HIP_ERROR, NO_MEMORY, LOG_OVERFLOW = -1, -2, -3, -4, -5
+EV_CORRECTED, EV_CHECKSUM_ROW, EV_CHECKSUM_COL, EV_UNCORRECTABLE, EV_DETECTED, EV_NONFINITE = 1, 2, 3, 4, 5, 6
 FAULT_ADD, FAULT_XOR = 0, 1
 
 EVENT_DTYPE = np.dtype([("problem", "<i4"), ("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"),
@@ -33,7 +34,7 @@ FAULT_DTYPE = np.dtype([("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"), 
 FAULT_LOG_DTYPE = np.dtype([("problem", "<i4"), ("tile_m", "<i4"), ("tile_n", "<i4"), ("kstep", "<i4"),
                             ("row", "<i4"), ("col", "<i4"), ("kind", "<i4"), ("check_step", "<i4"),
                             ("old_v", "<f4"), ("new_v", "<f4"), ("r_row", "<f4"), ("r_col", "<f4"),
-                            ("tau_row", "<f4"), ("tau_col", "<f4"), ("pad0_", "<f4"), ("pad1_", "<f4")])
+                            ("tau_row", "<f4"), ("tau_col", "<f4"), ("delta", "<f8")])
 
 
 class Config(ctypes.Structure):
@@ -52,7 +53,7 @@ class Config(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("checks", ctypes.c_uint64), ("detected", ctypes.c_uint64), ("corrected", ctypes.c_uint64),
                 ("uncorrectable", ctypes.c_uint64), ("checksum_only", ctypes.c_uint64),
-                ("n_events", ctypes.c_uint32), ("cap_events", ctypes.c_uint32),
+                ("nonfinite_input", ctypes.c_uint64), ("n_events", ctypes.c_uint32), ("cap_events", ctypes.c_uint32),
                 ("events", ctypes.c_void_p), ("config", Config), ("bad_arg", ctypes.c_int32),
                 ("tol_used", ctypes.c_float), ("bad_problem", ctypes.c_int32), ("recomputed", ctypes.c_uint32),
                 ("recompute_failed", ctypes.c_uint32), ("pad_", ctypes.c_int32)]
@@ -110,6 +111,9 @@ def lib():
         f64 = ctypes.c_double
         L.ftgemm_run_f64.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, i32, f64, vp,
                                      ctypes.POINTER(Report)]
+        dp2 = ctypes.POINTER(ctypes.c_double)
+        L.ftgemm_run_z64.argtypes = [vp, i64, i64, i64, dp2, vp, i64, vp, i64, dp2, vp, i64, i32, f64, vp,
+                                     ctypes.POINTER(Report)]
         L.ftgemm_set_injection.argtypes = [vp, vp, i32]
         L.ftgemm_get_injection_log.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
         L.ftgemm_batched.argtypes = [vp, i32, vp, i32, f32, vp, ctypes.POINTER(Report)]
@@ -123,7 +127,8 @@ def lib():
         for name in ("ftgemm_create", "ftgemm_destroy", "ftgemm_set_scales", "ftgemm_set_config",
                      "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
                      "ftgemm_get_injection_log", "ftgemm_batched", "ftgemm_batched_config", "ftgemm_tune", "ftgemm_get_tuned",
-                     "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused", "ftgemm_run_f64"):
+                     "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused", "ftgemm_run_f64",
+                     "ftgemm_run_z64"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -145,14 +150,19 @@ def ftgemm_status_string(status: int) -> str:
     return lib().ftgemm_status_string(status).decode()
 
 
+_handle_dtype: dict = {}   # operand type of each live handle, for the tensor entry point
+
+
 def ftgemm_create(dtype: int = F32, device: int = 0) -> int:
     h = ctypes.c_void_p()
     _check(lib().ftgemm_create(ctypes.byref(h), dtype, device), "ftgemm_create")
+    _handle_dtype[h.value] = (dtype, device)
     return h.value
 
 
 def ftgemm_destroy(handle: int) -> None:
     _check(lib().ftgemm_destroy(handle), "ftgemm_destroy")
+    _handle_dtype.pop(handle, None)
 
 
 def ftgemm_set_scales(handle: int, scale_a: float, scale_b: float) -> None:
@@ -185,28 +195,105 @@ def ftgemm_run(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: i
                beta: float, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
                stream: int = 0, report: ReportBuffer | None = None) -> int:
     """C = alpha A B + beta C on device pointers (column-major).  Returns the
-    status (0 or 1); raises FtgemmError on negative statuses."""
+    status (0, 1 or 2); raises FtgemmError on negative statuses."""
     st = lib().ftgemm_run(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
                           report.ptr() if report is not None else None)
     return _check(st, "ftgemm_run")
+
+
+def _swap_report(report: ReportBuffer) -> None:
+    """Events and configuration of a run on the transposed problem C^T, in
+    the coordinates of C: rows and columns (and everything attached to them)
+    trade places."""
+    ev = report.events_buf[: report.report.n_events]
+    for a, b in (("tile_m", "tile_n"), ("row", "col"), ("n_rows", "n_cols"), ("r_row", "r_col"),
+                 ("tau_row", "tau_col")):
+        x = ev[a].copy()
+        ev[a] = ev[b]
+        ev[b] = x
+    c = report.report.config
+    c.m_tile, c.n_tile = c.n_tile, c.m_tile
+    c.check_m, c.check_n = c.check_n, c.check_m
+
+
+def ftgemm_matmul(handle: int, A, B, C=None, alpha: float = 1.0, beta: float = 0.0, ft_level: int = FT_CORRECT,
+                  tol: float = 0.0, report: ReportBuffer | None = None):
+    """Row-major entry for PyTorch tensors: C = alpha A B + beta C with A (m x k),
+    B (k x n) and C (m x n, float32) on the handle's device, in PyTorch's
+    row-major layout (unit column stride; the row stride is the leading
+    dimension).  A and B are float32 for an F32 handle, bfloat16 for BF16 and
+    float8_e4m3fn (or uint8 codes) for F8E4M3.  C = None allocates a zeroed C.
+
+    A row-major m x n matrix is the column-major storage of its transpose, so
+    this runs ftgemm_run on C^T = B^T A^T: the operands trade places, so do m
+    and n, and the leading dimensions are the row strides.  The checks are
+    symmetric in rows and columns (the row check of C^T is the column check of
+    C), and the report's events and configuration are swapped back to C's
+    coordinates.  Fault sites set with ftgemm_set_injection address the
+    problem the library sees, C^T (tile_m/tile_n and row/col swapped).
+    Runs on torch's current stream.  Returns (C, status)."""
+    import torch
+
+    if handle not in _handle_dtype:
+        raise ValueError("unknown handle (create it with ftgemm_create)")
+    dtype, device = _handle_dtype[handle]
+    want = {F32: (torch.float32,), BF16: (torch.bfloat16,),
+            F8E4M3: tuple(t for t in (getattr(torch, "float8_e4m3fn", None), torch.uint8) if t is not None)}
+    if dtype not in want:
+        raise ValueError("ftgemm_matmul takes F32, BF16 and F8E4M3 handles")
+    for name, t in (("A", A), ("B", B)):
+        if t.dim() != 2 or t.dtype not in want[dtype] or not t.is_cuda or t.device.index != device:
+            raise ValueError(f"{name}: a 2-D {want[dtype][0]} tensor on cuda:{device} is required")
+        if t.stride(1) != 1 or t.stride(0) < max(1, t.shape[1]):
+            raise ValueError(f"{name}: rows must be contiguous (column stride 1, row stride >= columns)")
+    m, k = A.shape
+    if B.shape[0] != k:
+        raise ValueError(f"inner dimensions differ: A is {tuple(A.shape)}, B is {tuple(B.shape)}")
+    n = B.shape[1]
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float32, device=A.device)
+    if (C.dim() != 2 or tuple(C.shape) != (m, n) or C.dtype != torch.float32 or C.device != A.device
+            or C.stride(1) != 1 or C.stride(0) < max(1, n)):
+        raise ValueError(f"C: a row-major ({m}, {n}) float32 tensor on A's device is required")
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    st = ftgemm_run(handle, n, m, k, alpha, B.data_ptr(), max(1, B.stride(0)), A.data_ptr(),
+                    max(1, A.stride(0)), beta, C.data_ptr(), max(1, C.stride(0)), ft_level, tol, stream, report)
+    if report is not None:
+        _swap_report(report)
+    return C, st
 
 
 def ftgemm_run_f64(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: int, B: int, ldb: int,
                    beta: float, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
                    stream: int = 0, report: ReportBuffer | None = None) -> int:
     """FP64 C = alpha A B + beta C on device pointers to double (column-major),
-    for a handle created with F64.  Returns the status (0 or 1); raises
+    for a handle created with F64.  Returns the status (0, 1 or 2); raises
     FtgemmError on negative statuses."""
     st = lib().ftgemm_run_f64(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
                               report.ptr() if report is not None else None)
     return _check(st, "ftgemm_run_f64")
 
 
+def ftgemm_run_z64(handle: int, m: int, n: int, k: int, alpha: complex, A: int, lda: int, B: int, ldb: int,
+                   beta: complex, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
+                   stream: int = 0, report: ReportBuffer | None = None) -> int:
+    """Double-complex C = alpha A B + beta C on device pointers to (re, im)
+    binary64 pairs (column-major, leading dimensions in complex elements), for
+    a handle created with C64.  Events carry the component in `problem` (0
+    real, 1 imaginary).  Returns the status (0, 1 or 2); raises FtgemmError
+    on negative statuses."""
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = lib().ftgemm_run_z64(handle, m, n, k, al, A, lda, B, ldb, be, C, ldc, ft_level, tol, stream,
+                              report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_run_z64")
+
+
 def ftgemm_run_nonfused(handle: int, m: int, n: int, k: int, A: int, lda: int, B: int, ldb: int, C: int,
                         ldc: int, check_k: int = 0, tol: float = 0.0, stream: int = 0,
                         report: ReportBuffer | None = None, alpha: float = 1.0, beta: float = 0.0) -> int:
     """The same ABFT as ftgemm_run, not fused (separate launches around the
-    plain FP32 kernel on k-chunks of check_k).  Returns the status (0 or 1);
+    plain FP32 kernel on k-chunks of check_k).  Returns the status (0, 1 or 2);
     raises FtgemmError on negative statuses."""
     st = lib().ftgemm_run_nonfused(handle, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, check_k, tol, stream,
                                    report.ptr() if report is not None else None)
@@ -226,7 +313,7 @@ def ftgemm_get_injection_log(handle: int, cap: int = 16384) -> np.ndarray:
     n = ctypes.c_int(0)
     _check(lib().ftgemm_get_injection_log(handle, out.ctypes.data, cap, ctypes.byref(n)),
            "ftgemm_get_injection_log")
-    return out[: min(n.value, cap)].copy()
+    return out[: n.value].copy()
 
 
 def make_problems(count: int) -> np.ndarray:
@@ -238,7 +325,7 @@ def ftgemm_batched(handle: int, problems: np.ndarray, ft_level: int = FT_CORRECT
                    stream: int = 0, report: ReportBuffer | None = None) -> int:
     """All problems of a PROBLEM_DTYPE array in one persistent launch.  Keep
     `problems` unchanged between calls to reuse the handle's plan (required
-    under stream capture).  Returns the status (0 or 1); raises on errors."""
+    under stream capture).  Returns the status (0, 1 or 2); raises on errors."""
     arr = np.ascontiguousarray(problems, dtype=PROBLEM_DTYPE)
     st = lib().ftgemm_batched(handle, len(arr), arr.ctypes.data if len(arr) else None, ft_level, tol, stream,
                               report.ptr() if report is not None else None)

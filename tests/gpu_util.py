@@ -57,9 +57,25 @@ def event_keys(ev) -> list:
                    int(e["kind"])) for e in ev)
 
 
-def log_to_injections(log) -> np.ndarray:
-    return O.make_injections([(int(l["tile_m"]), int(l["tile_n"]), int(l["kstep"]), int(l["row"]),
-                               int(l["col"]), float(l["old_v"]), float(l["new_v"])) for l in log])
+def _fault_values(l):
+    """(old, new) for the oracle: a finite fault is applied as its exact offset
+    (the log's binary64 delta, taken as old = 0, new = delta), a non-finite one
+    as the value the accumulator took."""
+    d = float(l["delta"])
+    if np.isfinite(d) and np.isfinite(l["old_v"]) and np.isfinite(l["new_v"]):
+        return 0.0, d
+    return float(l["old_v"]), float(l["new_v"])
+
+
+def log_to_injections(log, comp_field=None) -> np.ndarray:
+    """Oracle injections from the GPU's applied-fault log (comp_field: the log
+    field that names a complex component)."""
+    rows = []
+    for l in log:
+        old, new = _fault_values(l)
+        row = (int(l["tile_m"]), int(l["tile_n"]), int(l["kstep"]), int(l["row"]), int(l["col"]), old, new)
+        rows.append(row + ((-1, int(l[comp_field])) if comp_field else ()))
+    return O.make_injections(rows)
 
 
 def _gpu_force(events, inj, check_step) -> int:
@@ -114,3 +130,78 @@ def replay_against_gpu(A, B, cfg, rep, log, C0=None, alpha=1.0, beta=0.0, ft_lev
         res = O.replay(A, B, rc, C0=C0, alpha=alpha, beta=beta, injections=inj, tiles=tiles)
         return res, first, len(grey), invalid
     return res, res.classes, 0, 0
+
+
+U32 = 2.0 ** -24      # unit roundoff of binary32
+
+
+def _abs_product(A, B):
+    return np.abs(np.asarray(A, np.float64)) @ np.abs(np.asarray(B, np.float64))
+
+
+def elementwise_ratio(C, ref, A, B, cfg=None, alpha=1.0, beta=0.0, C0=None, u=U32, events=(), oracle_events=(),
+                      log=(), tile=None, acc_u=None, c=2.0):
+    """Largest per-element ratio |C - ref|_ij / bound_ij over C (or the check
+    tile `tile` = (tm, tn) of C when given, with C, ref, C0 the full arrays).
+
+    bound_ij = (k + 2) u_acc (|alpha| (|A||B|)_ij + |beta| |C0_ij|): the
+    gamma_K bound of an accumulation in any order with one rounding per
+    addition, plus the two roundings of the epilogue (u_acc = acc_u, else u).
+    An element rebuilt by a correction comes from the row checksum, so its
+    error is that of a clean residual, at most beta_row = tau_row / c of the
+    oracle's event (c: the threshold factor of the run; its later k-steps
+    accumulate as usual); an element
+    that keeps a fault delta from the log adds (k + 2) u_acc |delta|.  Events
+    and log entries are in check-tile coordinates (cfg gives the check tile)."""
+    ua = u if acc_u is None else acc_u
+    k = A.shape[1]
+    i0 = j0 = 0
+    if tile is not None:
+        cm, cn = check_cfg(cfg)[:2]
+        i0, j0 = tile[0] * cm, tile[1] * cn
+        si, sj = slice(i0, min(i0 + cm, C.shape[0])), slice(j0, min(j0 + cn, C.shape[1]))
+        C, ref, A, B = C[si, sj], ref[si, sj], A[si], B[:, sj]
+        C0 = C0[si, sj] if C0 is not None else None
+    bound = (k + 2) * ua * abs(alpha) * _abs_product(A, B)
+    if C0 is not None and beta != 0.0:
+        bound += (k + 2) * ua * abs(beta) * np.abs(np.asarray(C0, np.float64))
+    if cfg is not None:
+        cm, cn = check_cfg(cfg)[:2]
+        tau_of = {}     # corrected element -> tau_row of its check (the oracle's where it has one)
+        for e in list(events) + list(oracle_events):
+            if int(e["kind"]) == F.EV_CORRECTED:
+                tau_of[(int(e["tile_m"]), int(e["tile_n"]), int(e["row"]), int(e["col"]))] = \
+                    abs(float(e["tau_row"]))
+        for key, tau in tau_of.items():
+            i, j = key[0] * cm + key[2] - i0, key[1] * cn + key[3] - j0
+            if 0 <= i < bound.shape[0] and 0 <= j < bound.shape[1]:
+                bound[i, j] += abs(alpha) * tau / c     # beta_row = tau_row / c
+        for l in log:
+            i, j = int(l["tile_m"]) * cm + int(l["row"]) - i0, int(l["tile_n"]) * cn + int(l["col"]) - j0
+            if 0 <= i < bound.shape[0] and 0 <= j < bound.shape[1]:
+                d = float(l["new_v"]) - float(l["old_v"])
+                if np.isfinite(d):
+                    bound[i, j] += (k + 2) * ua * abs(alpha) * abs(d)
+    err = np.abs(np.asarray(C, np.float64) - np.asarray(ref, np.float64))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(err == 0.0, 0.0, err / bound)
+    return float(np.max(r)) if r.size else 0.0
+
+
+def corrected_value_errors(events, oracle_events, c):
+    """For every CORRECTED event of the GPU, |value_after_gpu - value_after_oracle|
+    in units of the oracle's beta_row = tau_row / c at that check (the rebuilt
+    element's error is at most beta_row).  Returns the largest such ratio
+    and the number of events compared."""
+    ora = {(int(e["tile_m"]), int(e["tile_n"]), int(e["kstep"]), int(e["row"]), int(e["col"])): e
+           for e in oracle_events if int(e["kind"]) == F.EV_CORRECTED}
+    worst, n = 0.0, 0
+    for e in events:
+        if int(e["kind"]) != F.EV_CORRECTED:
+            continue
+        key = (int(e["tile_m"]), int(e["tile_n"]), int(e["kstep"]), int(e["row"]), int(e["col"]))
+        o = ora[key]
+        beta_row = float(o["tau_row"]) / c
+        worst = max(worst, abs(float(e["value_after"]) - float(o["value_after"])) / beta_row)
+        n += 1
+    return worst, n

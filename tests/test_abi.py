@@ -43,7 +43,8 @@ def test_struct_sizes_match_header_layout():
     assert F.FAULT_DTYPE.itemsize == 32
     assert F.FAULT_LOG_DTYPE.itemsize == 64
     assert ctypes.sizeof(F.Config) == 24
-    assert ctypes.sizeof(F.Report) == 5 * 8 + 4 + 4 + 8 + 24 + 4 + 4 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(F.Report) == 6 * 8 + 4 + 4 + 8 + 24 + 4 + 4 + 4 + 4 + 4 + 4
+    assert F.Report.nonfinite_input.offset == 40
     assert F.PROBLEM_DTYPE.itemsize == 96
     assert ctypes.sizeof(F.Tuned) == 56
     assert W.SITE_DTYPE == F.FAULT_DTYPE
@@ -89,6 +90,31 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(st), name
         for fld, _ in st._fields_:
             assert got[(name, fld)] == getattr(st, fld).offset, (name, fld)
+
+
+def test_enum_values_match_header():
+    """Status codes, event kinds, levels and dtypes of the binding equal the
+    header's enumerators (parsed from include/ftgemm.h)."""
+    text = open(os.path.join(ROOT, "include", "ftgemm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    vals = {k: int(v, 0) for k, v in re.findall(r"\b(FTGEMM_[A-Z0-9_]+)\s*=\s*(-?(?:0x)?[0-9A-Fa-f]+)", text)}
+    mirror = {"FTGEMM_OK": F.OK, "FTGEMM_UNCORRECTABLE": F.UNCORRECTABLE,
+              "FTGEMM_NONFINITE_INPUT": F.NONFINITE_INPUT, "FTGEMM_INVALID": F.INVALID,
+              "FTGEMM_UNSUPPORTED": F.UNSUPPORTED, "FTGEMM_HIP_ERROR": F.HIP_ERROR,
+              "FTGEMM_NO_MEMORY": F.NO_MEMORY, "FTGEMM_LOG_OVERFLOW": F.LOG_OVERFLOW,
+              "FTGEMM_EV_CORRECTED": F.EV_CORRECTED, "FTGEMM_EV_CHECKSUM_ROW": F.EV_CHECKSUM_ROW,
+              "FTGEMM_EV_CHECKSUM_COL": F.EV_CHECKSUM_COL, "FTGEMM_EV_UNCORRECTABLE": F.EV_UNCORRECTABLE,
+              "FTGEMM_EV_DETECTED": F.EV_DETECTED, "FTGEMM_EV_NONFINITE": F.EV_NONFINITE,
+              "FTGEMM_FT_OFF": F.FT_OFF, "FTGEMM_FT_DETECT": F.FT_DETECT, "FTGEMM_FT_CORRECT": F.FT_CORRECT,
+              "FTGEMM_FT_RECOMPUTE": F.FT_RECOMPUTE, "FTGEMM_F32": F.F32, "FTGEMM_BF16": F.BF16,
+              "FTGEMM_F8E4M3": F.F8E4M3, "FTGEMM_F64": F.F64, "FTGEMM_C64": F.C64, "FTGEMM_FAULT_ADD": F.FAULT_ADD,
+              "FTGEMM_FAULT_XOR": F.FAULT_XOR}
+    for name, v in mirror.items():
+        assert vals[name] == v, name
+    # the status strings distinguish every status
+    strings = {F.ftgemm_status_string(v) for v in (F.OK, F.UNCORRECTABLE, F.NONFINITE_INPUT, F.INVALID,
+                                                   F.UNSUPPORTED, F.HIP_ERROR, F.NO_MEMORY, F.LOG_OVERFLOW)}
+    assert len(strings) == 8 and "unknown status" not in strings
 
 
 @pytest.mark.parametrize("args,bad", [

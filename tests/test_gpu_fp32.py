@@ -10,7 +10,7 @@ from oracle import oracle as O
 from paper_2305_01024_amd import ftgemm as F
 from paper_2305_01024_amd import workloads as W
 
-from gpu_util import event_keys, replay_against_gpu, rel_fro, run
+from gpu_util import corrected_value_errors, elementwise_ratio, event_keys, replay_against_gpu, rel_fro, run
 
 pytestmark = pytest.mark.gpu
 TOL_F32 = 1e-5
@@ -49,6 +49,7 @@ def test_clean_matches_oracle(h, shape, level):
     ref = O.gemm(A, B)
     assert st == F.OK
     assert rel_fro(C, ref) <= TOL_F32
+    assert elementwise_ratio(C, ref, A, B) <= 1.0
     assert rep.report.n_events == 0 and rep.report.detected == 0
 
 
@@ -63,10 +64,12 @@ def test_every_variant_ragged_alpha_beta(h, variant, g):
     st, C, rep = run(h, A, B, C0, alpha=0.5, beta=-1.5)
     assert st == F.OK and rep.report.config.as_tuple()[:4] == (*variant, g)
     assert rep.report.config.check_shape() == tuple(variant[:2])
-    assert rel_fro(C, O.gemm(A, B, C0, alpha=0.5, beta=-1.5)) <= TOL_F32
+    ref = O.gemm(A, B, C0, alpha=0.5, beta=-1.5)
+    assert rel_fro(C, ref) <= TOL_F32
+    assert elementwise_ratio(C, ref, A, B, alpha=0.5, beta=-1.5, C0=C0) <= 1.0
     assert rep.report.n_events == 0
     nt = -(-m // variant[0]) * -(-n // variant[1])
-    assert rep.report.checks == nt * -(-(-(-k // variant[2])) // g)
+    assert rep.report.checks == nt * -(-(-(-k // variant[2])) // g)   # counted on the device
 
 
 def test_integer_operands_are_exact(h):
@@ -126,6 +129,54 @@ def test_repeat_runs_are_bitwise_identical(h):
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
 
+def test_determinism_canary_8192(h):
+    """Twenty clean online runs of the benchmarked 8192^3 configuration give
+    bitwise the same C (compared on the device)."""
+    import torch
+    m = n = k = 8192
+    A = torch.from_numpy(np.ascontiguousarray(W.normal((m, k), 2, W.STREAM_A).T)).cuda()
+    B = torch.from_numpy(np.ascontiguousarray(W.normal((k, n), 2, W.STREAM_B).T)).cuda()
+    C0 = torch.from_numpy(np.ascontiguousarray(W.normal((m, n), 2, W.STREAM_C).T)).cuda()
+    s = torch.cuda.current_stream().cuda_stream
+    first = None
+    for r in range(20):
+        C = C0.clone()
+        st = F.ftgemm_run(h, m, n, k, 1.0, A.data_ptr(), m, B.data_ptr(), k, 1.0, C.data_ptr(), m,
+                          F.FT_CORRECT, 0.0, s, None)
+        assert st == F.OK
+        if first is None:
+            first = C
+        else:
+            assert torch.equal(first, C), r
+
+
+def test_repeat_runs_with_corrections(h):
+    """Ten runs with the same faults: the event log and every element no
+    correction touched are bitwise the same; a corrected element is rebuilt
+    from a row checksum whose cross-wave sum of B e may add in a different
+    order, so it is compared within beta_row of the oracle's."""
+    m, n, k = 1024, 1024, 1024
+    A = W.normal((m, k), 213, 0)
+    B = W.normal((k, n), 213, 1)
+    cfg = (256, 256, 32, 8)
+    sites = W.fault_sites(W.rng(213, 3), m, n, k, 256, 256, 32, 8, 0, payload=1e4, per_tile=1)
+    F.ftgemm_set_config(h, cfg)
+    F.ftgemm_set_injection(h, sites)
+    runs = [run(h, A, B) for _ in range(10)]
+    log = F.ftgemm_get_injection_log(h)
+    F.ftgemm_set_injection(h, None)
+    keys = [event_keys(r[2].events) for r in runs]
+    assert all(kk == keys[0] for kk in keys) and len(keys[0]) == 16
+    mask = np.ones((m, n), dtype=bool)
+    for e in runs[0][2].events:
+        mask[int(e["tile_m"]) * 256 + int(e["row"]), int(e["tile_n"]) * 256 + int(e["col"])] = False
+    for r in runs[1:]:
+        assert np.array_equal(r[1][mask], runs[0][1][mask])
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, runs[0][2], log)
+    for st, C, rep in runs:
+        assert corrected_value_errors(rep.events, res.events, rep.report.tol_used)[0] <= 1.0
+
+
 # ---------------------------------------------------------------------------
 # fault injection
 # ---------------------------------------------------------------------------
@@ -154,6 +205,10 @@ def test_one_additive_fault_per_tile_256(h):
     assert event_keys(rep.events) == event_keys(res.events)
     assert rel_fro(C, res.C) <= TOL_F32
     assert rel_fro(C, O.gemm(A, B)) <= TOL_F32     # all corrected: the clean product
+    assert elementwise_ratio(C, res.C, A, B, cfg, events=rep.events, oracle_events=res.events, log=log) <= 1.0
+    worst, ncmp = corrected_value_errors(rep.events, res.events, rep.report.tol_used)
+    assert ncmp == 4 and worst <= 1.0
+    assert rep.report.checks == 4 * 8
 
 
 @pytest.mark.parametrize("cfg", [(128, 128, 32, 1), (256, 256, 32, 4), (64, 64, 32, 2)])
@@ -171,6 +226,9 @@ def test_many_faults_across_tiles_and_intervals(h, cfg):
     assert st == F.OK and rep.report.corrected == count
     assert event_keys(rep.events) == event_keys(res.events)
     assert rel_fro(C, O.gemm(A, B)) <= TOL_F32
+    assert elementwise_ratio(C, res.C, A, B, cfg, events=rep.events, oracle_events=res.events, log=log) <= 1.0
+    worst, ncmp = corrected_value_errors(rep.events, res.events, rep.report.tol_used)
+    assert ncmp == count and worst <= 1.0
 
 
 @pytest.mark.parametrize("bits", [range(23, 31), range(0, 31)])
@@ -189,6 +247,8 @@ def test_bit_flips_exact_site_log(h, bits):
     assert rep.report.corrected >= must
     assert event_keys(rep.events) == event_keys(res.events)
     assert rel_fro(C, res.C) <= TOL_F32
+    assert elementwise_ratio(C, res.C, A, B, cfg, events=rep.events, oracle_events=res.events, log=log) <= 1.0
+    assert corrected_value_errors(rep.events, res.events, rep.report.tol_used)[0] <= 1.0
     if bits == range(23, 31):
         assert must > 0
 
@@ -251,14 +311,18 @@ def test_full_size_8192_sampled_tiles(h):
     for (tm, tn) in tiles:
         sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
         assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
+        assert elementwise_ratio(C, res.C, A, B, cfg, alpha=1.0, beta=1.0, C0=C0, tile=(tm, tn)) <= 1.0
+    assert rep.report.checks == 1024 * 32
 
 
 def test_full_size_8192_one_fault_per_tile(h):
     """8192^3 N(0,1), beta = 1, automatic configuration, one +1e5 fault in
-    every one of the 1024 tiles at a seeded k-step, row and column: all are
-    corrected, and on three sampled tiles the oracle replay (same faults, same
-    threshold constant) classifies them must-detect, its event log equals the
-    GPU's and C matches it.  At this size the bound passes 1e3 about half way
+    every one of the 1024 tiles at a seeded k-step, row and column: the oracle
+    replays every tile with the same faults and threshold constant, classes
+    every fault must-detect, and its event log equals the GPU's; C equals the
+    replay element by element within the accumulation bound (corrected
+    elements within beta_row), and every corrected value is within beta_row
+    of the replay's.  At this size the bound passes 1e3 about half way
     through K (c 2u (K'+n+1) |a_i| sum_j |b_j| ~ 4e3 at K' = 8192 with c = 2
     and 256 N(0,1) columns), so a +1e3 fault in the second half lies inside
     the rounding bound and is left alone by design (465 of 1024 were
@@ -276,17 +340,16 @@ def test_full_size_8192_one_fault_per_tile(h):
     assert st == F.OK and rep.report.config.as_tuple()[:4] == cfg[:4]
     assert len(log) == len(sites) == 1024
     assert rep.report.corrected == 1024 and rep.report.uncorrectable == 0
-    tiles = [(0, 0), (31, 31), (13, 21)]
-    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
-    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
-    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, part, C0=C0, alpha=1.0, beta=1.0, tiles=tiles)
-    assert bad == 0 and len(part) == len(tiles)
-    assert np.all(cls["cls"] == O.CLS_MUST)
-    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
-    assert event_keys(ev) == event_keys(res.events)
-    for (tm, tn) in tiles:
-        sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
-        assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
+    assert rep.report.checks == 1024 * 32
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, log, C0=C0, alpha=1.0, beta=1.0)
+    assert bad == 0 and np.all(cls["cls"] == O.CLS_MUST)
+    assert event_keys(rep.events) == event_keys(res.events)
+    assert rel_fro(C, res.C) <= TOL_F32
+    ratio = elementwise_ratio(C, res.C, A, B, cfg, alpha=1.0, beta=1.0, C0=C0, events=rep.events,
+                              oracle_events=res.events, log=log)
+    worst, ncmp = corrected_value_errors(rep.events, res.events, rep.report.tol_used)
+    print(f"\n[8192 fault per tile] element-wise ratio {ratio:.3e}, corrected values {worst:.3e} of beta_row")
+    assert ratio <= 1.0 and ncmp == 1024 and worst <= 1.0
 
 
 def test_full_size_8192_bit_flips_exact_site_log(h):
@@ -311,6 +374,9 @@ def test_full_size_8192_bit_flips_exact_site_log(h):
     assert event_keys(rep.events) == event_keys(res.events)
     assert all((int(e["tile_m"]), int(e["tile_n"])) in tiles for e in rep.events)
     assert rep.report.corrected >= int(np.sum(cls["cls"] == O.CLS_MUST))
+    assert corrected_value_errors(rep.events, res.events, rep.report.tol_used)[0] <= 1.0
     for (tm, tn) in tiles:
         sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
         assert rel_fro(C[sl], res.C[sl]) <= TOL_F32, (tm, tn)
+        assert elementwise_ratio(C, res.C, A, B, cfg, alpha=1.0, beta=1.0, C0=C0, events=rep.events,
+                                 oracle_events=res.events, log=log, tile=(tm, tn)) <= 1.0, (tm, tn)

@@ -201,7 +201,10 @@ def test_detect_only_with_recompute(h, cfg):
     st, C, rep, log, res, cls = _inject(h, A, B, cfg, sites, level=F.FT_DETECT | F.FT_RECOMPUTE)
     assert event_keys(rep.events) == event_keys(res.events)
     assert all(int(e["kind"]) == F.EV_DETECTED for e in rep.events) and rep.report.detected == 3
-    assert rep.report.checks == _n_checks(m, n, k, cfg, F.FT_DETECT)
+    # counted on the device, the recompute launch's checks included (each recomputed compute
+    # tile checks its wave tiles once more)
+    wm, wn = WAVES[cfg[:2]]
+    assert rep.report.checks == _n_checks(m, n, k, cfg, F.FT_DETECT) + rep.report.recomputed * wm * wn
     assert rep.report.recomputed == len(tiles) and rep.report.recompute_failed == 0
     assert st == F.OK and rel_fro(C, O.gemm(A, B)) <= TOL_F32
 

@@ -43,6 +43,19 @@ MUTANTS = {
     "non-finite operands go through the decision table": (
         "if (!isfinite(sum_na) || !isfinite(sum_nb)) {", "if (0) {"),
     "non-finite tile reported at every check": ("            if (!nonfinite) {\n", "            if (1) {\n"),
+    # complex binary64 replay
+    "complex product conjugates B": ("P[i + j * mI] += zget(A, lda, i0 + i, k0 + p) * b;",
+                                     "P[i + j * mI] += zget(A, lda, i0 + i, k0 + p) * conj(b);"),
+    "complex row reference uses conj(B e)": ("s += a * CMPLX(v[2 * p], v[2 * p + 1]);",
+                                             "s += a * CMPLX(v[2 * p], -v[2 * p + 1]);"),
+    "complex bound counts K' products per component, not 2K'": (
+        "rbet[i] = oracle_beta(cfg->u, 2 * k1, nJ, sqrt(na2[i]), sum_nb);",
+        "rbet[i] = oracle_beta(cfg->u, k1, nJ, sqrt(na2[i]), sum_nb);"),
+    "complex norm drops the imaginary part": ("q += creal(a) * creal(a) + cimag(a) * cimag(a);",
+                                              "q += creal(a) * creal(a);"),
+    "complex correction from the other component's checksum": ("zcomp(R[fr], c) - s", "zcomp(R[fr], 1 - c) - s"),
+    "complex event labelled with the wrong component": ("e.comp = c;", "e.comp = 0;"),
+    "complex fault applied to the real part": ("*x = zwith(*x, f->comp, nv);", "*x = zwith(*x, 0, nv);"),
 }
 
 
@@ -58,6 +71,7 @@ def test_mutant_is_caught(name, tmp_path):
                     str(msrc), "-o", str(lib), "-lm"], check=True)
     env = dict(os.environ, FTGEMM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_complex.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
