@@ -233,6 +233,26 @@ int ftgemm_run_nonfused(ftgemm_t handle, int64_t m, int64_t n, int64_t k, float 
                         float* C, int64_t ldc, int check_k, float tol, hipStream_t stream,
                         ftgemm_report_t* report);
 
+/* ftgemm_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  No
+ * handle: the call runs on the current device, with operands of type `dtype`
+ * (FTGEMM_F32, FTGEMM_BF16 or FTGEMM_F8E4M3; per-tensor scales of low-
+ * precision operands go into alpha), the automatic configuration and no fault
+ * injection; every other argument, the levels, the report and the return
+ * codes are those of ftgemm_run.  The call allocates nothing: its counters,
+ * event log (1024 events; FTGEMM_LOG_OVERFLOW past that, with the counts
+ * exact) and recompute queue live in a static device array of 128.5 KiB that
+ * each device holds until the process ends.  FTGEMM_FT_RECOMPUTE on a shape
+ * of more than 16384 output tiles returns FTGEMM_NO_MEMORY.  All calls on a
+ * device share that array: calls that overlap on one device (several
+ * streams, several host threads) race and must be serialised by the caller.
+ * The first call on a device takes the array's device address (no
+ * allocation); with report == NULL a call launches only kernels, so it can be
+ * captured into a HIP graph. */
+int ftgemm_run_noalloc(int dtype, int64_t m, int64_t n, int64_t k, float alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int ft_level, float tol,
+                       hipStream_t stream, ftgemm_report_t* report);
+
 /* C = alpha * A * B + beta * C in binary64 for a handle created with
  * FTGEMM_F64 (ftgemm_run refuses such a handle: its C is float).  A, B, C
  * are double, column-major, device pointers as in ftgemm_run; products,

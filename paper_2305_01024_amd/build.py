@@ -21,7 +21,7 @@ LIB = os.path.join(LIBDIR, "libftgemm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HIP_SOURCES = ["ftgemm_fp32.hip", "ftgemm_bf16.hip", "ftgemm_fp8.hip", "ftgemm_fp64.hip", "ftgemm_batched.hip",
-               "ftgemm_nonfused.hip", "ftgemm_complex.hip"]
+               "ftgemm_nonfused.hip", "ftgemm_noalloc.hip", "ftgemm_complex.hip"]
 CXX_SOURCES = ["ftgemm_api.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

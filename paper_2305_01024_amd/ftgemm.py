@@ -108,6 +108,8 @@ def lib():
                                  ctypes.POINTER(Report)]
         L.ftgemm_run_nonfused.argtypes = [vp, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
                                           ctypes.POINTER(Report)]
+        L.ftgemm_run_noalloc.argtypes = [i32, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, f32, vp,
+                                         ctypes.POINTER(Report)]
         f64 = ctypes.c_double
         L.ftgemm_run_f64.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, i32, f64, vp,
                                      ctypes.POINTER(Report)]
@@ -128,7 +130,7 @@ def lib():
                      "ftgemm_select_config", "ftgemm_validate", "ftgemm_run", "ftgemm_set_injection",
                      "ftgemm_get_injection_log", "ftgemm_batched", "ftgemm_batched_config", "ftgemm_tune", "ftgemm_get_tuned",
                      "ftgemm_add_tuned", "ftgemm_tune_batched", "ftgemm_run_nonfused", "ftgemm_run_f64",
-                     "ftgemm_run_z64"):
+                     "ftgemm_run_noalloc", "ftgemm_run_z64"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -261,6 +263,17 @@ def ftgemm_matmul(handle: int, A, B, C=None, alpha: float = 1.0, beta: float = 0
     if report is not None:
         _swap_report(report)
     return C, st
+
+
+def ftgemm_run_noalloc(dtype: int, m: int, n: int, k: int, alpha: float, A: int, lda: int, B: int, ldb: int,
+                       beta: float, C: int, ldc: int, ft_level: int = FT_CORRECT, tol: float = 0.0,
+                       stream: int = 0, report: ReportBuffer | None = None) -> int:
+    """ftgemm_run without a handle and without allocating (static device
+    workspace; the current device; calls on one device must not overlap).
+    Returns the status (0, 1 or 2); raises FtgemmError on negative statuses."""
+    st = lib().ftgemm_run_noalloc(dtype, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ft_level, tol, stream,
+                                  report.ptr() if report is not None else None)
+    return _check(st, "ftgemm_run_noalloc")
 
 
 def ftgemm_run_f64(handle: int, m: int, n: int, k: int, alpha: float, A: int, lda: int, B: int, ldb: int,
