@@ -179,7 +179,8 @@ typedef struct {
 int ftgemm_create(ftgemm_t* handle, int dtype, int device);
 int ftgemm_destroy(ftgemm_t handle);
 
-/* Per-tensor dequantisation scales for BF16/FP8 operands (default 1):
+/* Per-tensor dequantisation scales for BF16/FP8 operands (default 1; the
+ * low-precision operand types extend section 6's list of further data types):
  * the product is computed as (scale_a * A) (scale_b * B).  The scales are
  * applied in the epilogue as alpha * scale_a * scale_b, after the checks,
  * so powers of two keep the result bit-identical to scaling the operands.
@@ -362,15 +363,23 @@ int ftgemm_add_tuned(ftgemm_t handle, const ftgemm_tuned_t* entry);
  * FP32 64x64, BF16 128x128).  Synchronises `stream`. */
 int ftgemm_tune_batched(ftgemm_t handle, hipStream_t stream, double* rates);
 
-/* Fault injection hook (compiled into dedicated kernel instantiations; the
- * production kernels contain no injection code).  `faults` is a host array
- * of n sites, copied to the device; n == 0 disables injection.  Sites must
- * be sorted by (problem, tile_m, tile_n, kstep); at most 32 per compute tile
- * (all its check tiles together). */
+/* Fault injection hook (section 5.3: errors placed in the accumulator
+ * registers to stand for bit flips, a set number per threadblock spread over
+ * the k loop at the check distance; section 4.1 fixes the single-upset model
+ * they follow).  Compiled into dedicated kernel instantiations; the
+ * production kernels contain no injection code.  `faults` is a host array
+ * of n sites, copied to the device (the handle owns the copy); n == 0
+ * disables injection.  Sites must be sorted by (problem, tile_m, tile_n,
+ * kstep); at most 32 per compute tile (all its check tiles together).
+ * Returns FTGEMM_INVALID for a negative n, a NULL array with n > 0, a
+ * negative coordinate, an unknown kind or a bit index beyond the accumulator
+ * (31, or 63 for FP64 and FP64 complex); the order is not checked. */
 int ftgemm_set_injection(ftgemm_t handle, const ftgemm_fault_t* faults, int n);
 
 /* Copy the applied-fault log of the last call into `out` (host array of cap
- * entries); *n receives the number of entries copied.  Returns
+ * entries, caller-owned); *n receives the number of entries copied.  The log
+ * is what section 5.3 validates against: each applied fault with the residuals
+ * and thresholds of the first check that saw it.  Returns
  * FTGEMM_LOG_OVERFLOW if more faults were applied than were copied (the
  * device log holds 16384 entries; `cap` may be smaller). */
 int ftgemm_get_injection_log(ftgemm_t handle, ftgemm_fault_log_t* out, int cap, int* n);

@@ -14,7 +14,10 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libftgemm.so")
+# FTGEMM_LIB selects another build of the same sources (the sanitizer tests
+# load one whose host API is built with ASan/UBSan)
+LIB_PATH = os.environ.get("FTGEMM_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib",
+                                                         "libftgemm.so")
 
 F32, BF16, F8E4M3, F64, C64 = 0, 1, 2, 3, 4
 FT_OFF, FT_DETECT, FT_CORRECT = 0, 1, 2
