@@ -296,6 +296,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM fetch + write, calibrated)",
                      "traffic_source": traffic_src,
+                     "mfma_busy": measured_mfma_busy(args.dtype, N) if ms_ft else None,
                      "kernel": kname + (" FT=2" if ms_ft else " FT=0")},
         "levels": levels,
         "injection": injection,
@@ -318,8 +319,8 @@ def bench_f64(args):
     alpha = 1, beta = 1; online FT (a check every 256 k), detect-only and
     plain launches timed with HIP events on the launch stream; one +1e3 fault
     per tile at a seeded k-step, row and column in a separate run, all of
-    which must be corrected.  The kernel is SIMT FP64 FMA (no matrix cores),
-    so the roofline is the FP64 FMA rate."""
+    which must be corrected.  The kernel runs on the FP64 matrix cores
+    (16x16x4 instruction), so the roofline is their dense peak."""
     import torch
 
     from paper_2305_01024_amd import ftgemm as F
@@ -364,7 +365,7 @@ def bench_f64(args):
            "ft_overhead_pct": round(100 * (ms_ft / ms_plain - 1), 2),
            "detect_only_overhead_pct": round(100 * (ms_det / ms_plain - 1), 2),
            "injection_one_per_tile": inj,
-           "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+           "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None},
            "cpu_baseline": None}
     log(f"f64: {out}")
@@ -845,6 +846,25 @@ def measured_traffic(dtype: str, size: int):
     fetch = rec["ft_fetch_kib"] * kib * rec["copy_bytes_read"] / (rec["copy_fetch_kib"] * kib)
     write = rec["ft_write_kib"] * kib * rec["copy_bytes_written"] / (rec["copy_write_kib"] * kib)
     return int(round(fetch + write)), os.path.relpath(path, ROOT)
+
+
+def measured_mfma_busy(dtype: str, size: int):
+    """Matrix-core busy fraction of the FT and plain kernels from the committed
+    hardware-counter summary (SQ_VALU_MFMA_BUSY_CYCLES per SIMD over the
+    kernel's GPU-active cycles, and the clock those cycles imply), or None when
+    there is none for this workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"ftgemm_{dtype}_{size}_mfma_util.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    src = os.path.relpath(path, ROOT)
+    if rec.get("source_sha256") != kernel_source_hash(dtype):
+        return {"ft_pct": None, "plain_pct": None, "source": src + " (stale: kernel sources changed)"}
+    return {"ft_pct": rec["ft_mfma_busy_pct"], "plain_pct": rec["plain_mfma_busy_pct"],
+            "ft_clock_ghz": rec["ft_clock_ghz"], "plain_clock_ghz": rec["plain_clock_ghz"], "source": src}
 
 
 def _cpu_model() -> str:

@@ -188,6 +188,9 @@ struct CheckLds {
     int tainted;            // a check left the tile possibly wrong (cleared at tile start)
     int nonfinite;          // check tiles already reported for non-finite operands, one bit
                             // per check tile (bit 0: the compute tile; cleared at tile start)
+    unsigned nchecks;       // checks of this tile so far (cleared at tile start); added to the
+                            // launch's counter once, at the end of the tile, so that the loop
+                            // carries no global atomic whose completion a later wait would see
 };
 
 // Extra LDS of the wavefront-tile check: per wave, the flag census of each
@@ -430,7 +433,7 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
         s.census[th.wave][3] = fc_w;
     }
     if (th.tid == 0) {
-        atomicAdd(&a.counters[CNT_CHECKS], 1u);
+        s.nchecks += 1u;
         if (!finite && !(s.nonfinite & 1)) {
             s.nonfinite |= 1;
             log_nonfinite(a, th.tm, th.tn, t);
@@ -718,7 +721,7 @@ __device__ void check_wave(Acc<G>& acc, WaveCheckLds<G>& s, const LaunchArgs& a,
     // the wave's own check tile (wm, wn), if it holds part of C: counted, and
     // reported once if its operands are not finite
     if (lane == 0 && wm * TM < th.mI && wn * TN < th.nJ) {
-        atomicAdd(&a.counters[CNT_CHECKS], 1u);
+        atomicAdd(&s.nchecks, 1u);
         if (!finite_tile(wm, wn) && !(s.nonfinite & (1 << wave))) {
             atomicOr(&s.nonfinite, 1 << wave);
             log_nonfinite(a, th.tm * WM + wm, th.tn * WN + wn, t);
@@ -821,6 +824,7 @@ template <class G, int FT>
 __device__ __forceinline__ void finish_tile(const Acc<G>& acc, const CheckLds<G>& s, const LaunchArgs& a,
                                             const Thread& th, float scale) {
     const bool tainted = FT > 0 && s.tainted != 0;   // written before the last check's final barrier
+    if (FT > 0 && th.tid == 0) atomicAdd(&a.counters[CNT_CHECKS], s.nchecks);   // ditto
     if (tainted && a.retry_tiles && !a.retry_pass) {
         if (th.tid == 0) {
             const int ntm = (a.M + G::BM - 1) / G::BM;

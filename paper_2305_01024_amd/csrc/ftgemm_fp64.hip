@@ -1,14 +1,18 @@
 // ftgemm_fp64.hip -- FP64 online ABFT GEMM for gfx950 (MI355X).
 //
-// C = alpha * A * B + beta * C in binary64, A, B, C column-major.  On MI355X
-// the FP64 vector FMA rate equals the FP64 matrix-core rate, so this kernel
-// keeps the paper's own outer-product SIMT form (section 3, 8 x 8 thread
-// tiles): a workgroup of 256 threads computes a 128 x 128 tile, each thread an
-// 8 x 8 micro-tile with v_fma_f64, k-steps of 16 staged through
-// double-buffered LDS.  tid = 16 ty + tx holds rows 32 (r / 2) + 2 ty + r % 2
-// and columns 32 (c / 2) + 2 tx + c % 2 (r, c = 0..7): each 16-byte fragment
-// read of a wave then covers 16 consecutive pairs (no LDS bank conflicts),
-// where contiguous 8-wide micro-tiles would put 16 lanes 64 bytes apart.
+// C = alpha * A * B + beta * C in binary64, A, B, C column-major, on the FP64
+// matrix cores (v_mfma_f64_16x16x4_f64).  A workgroup of 256 threads (four
+// wavefronts, a 2 x 2 grid of 64 x 64 sub-tiles, each 4 x 4 blocks of
+// 16 x 16) computes a 128 x 128 tile, k-steps of 16 staged through
+// double-buffered LDS, both panels k-major (A as loaded, B transposed on the
+// way in), so every operand a lane supplies is one consecutive 16-lane row of
+// a panel.  The MFMA computes the transposed block P^T = B^T A^T: lane l
+// supplies B[k0 + l / 16][j0 + l % 16] and A[i0 + l % 16][k0 + l / 16] and
+// holds P[i0 + l % 16][j0 + 4 q + l / 16] in component q (the instruction's
+// lane layout, measured on the device), so a lane owns one row of C per block
+// and stores along i are coalesced.  (The SIMT form of the paper, 8 x 8
+// v_fma_f64 micro-tiles per thread, ran this tile at 40.2 TFLOP/s plain and
+// 29.9 online at 8192^3; this form at 56.6 and 39.1.)
 //
 // Fault tolerance, threadblock-level (section 4.2.3), online (section 2.2,
 // Eq. 4), all in FP64:
@@ -22,8 +26,9 @@
 //   * reference checksums (Eq. 3-4): threads 0..127 own rows (R_i, ||a_i||^2),
 //     threads 128..255 own columns (S_j, ||b_j||^2);
 //   * a check every `check_interval` k-steps and after the last: row and
-//     column sums of the micro-tiles (lane shuffles in a wave, LDS across
-//     waves), residuals against R and S, the threshold with u = 2^-53;
+//     column sums of the accumulator blocks (lane exchanges in a wave, LDS
+//     across the wave grid), residuals against R and S, the threshold with
+//     u = 2^-53;
 //     one flagged row and one flagged column: the element at their
 //     intersection is rebuilt from the row checksum (section 4.2.1, 5.3);
 //     other patterns are logged and the flagged checksums re-based.
@@ -36,7 +41,7 @@
 namespace ftgemm_impl {
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 16, NT = 256, TPT = 8;   // tile, k-step, threads, micro-tile
+constexpr int BM = 128, BN = 128, BK = 16, NT = 256;   // tile, k-step, threads
 constexpr int LP = BM + 2;            // LDS row pitch in doubles (16-byte aligned rows, staggered banks)
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53, unit roundoff of binary64
 constexpr int kMaxF64Faults = 32;
@@ -46,9 +51,8 @@ struct F64Lds {
     double Bs[2][BK][LP];         // B panel, k-major (j contiguous)
     double wsum[2][BK];           // e^T A of the panel
     double vsum[3][BK];           // B e of the panel (added across waves, 3 rotating slots)
-    double rowsum[BM];            // row sums of the tile (SIMT form)
-    double rowpart[2][BM];        // row sums per wave column (matrix-core form)
-    double colpart[4][BN];        // column sums per wave (SIMT: four ty per wave; matrix-core: per wave row)
+    double rowpart[2][BM];        // row sums per wave column
+    double colpart[2][BN];        // column sums per wave row
     double excl[2];               // correction: row sum without the faulty element, per wave column
     double nsum[4];               // per-wave sums of ||a_i|| (waves 0, 1) and ||b_j|| (waves 2, 3)
     int census[4][4];             // per wave: #rows, first row, #cols, first col flagged
@@ -57,6 +61,7 @@ struct F64Lds {
     int fslot[kMaxF64Faults];
     int nf;
     int nonfinite;                // the tile was reported for non-finite operands
+    unsigned nchecks;             // checks of this tile (added to the launch's counter at its end)
 };
 
 // Lane exchanges of a double on its two 32-bit halves.  dpp64<CTRL>: the
@@ -106,49 +111,26 @@ __device__ __forceinline__ double wave_sum64(double x) {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// micro-tile index maps (see the header comment)
-__device__ __forceinline__ int tile_row(int ty, int r) { return 32 * (r >> 1) + 2 * ty + (r & 1); }
-__device__ __forceinline__ int line_owner(int i) { return (i & 31) >> 1; }       // ty (or tx) holding line i
-__device__ __forceinline__ int line_slot(int i) { return 2 * (i >> 5) + (i & 1); }  // r (or c) of line i
-
 __device__ __forceinline__ double flip64(double v, int bit) {
     return __longlong_as_double(__double_as_longlong(v) ^ (long long)(1ull << (bit & 63)));
 }
 
 // One 128 x 128 tile (tm, tn).  FT: 0 plain, 1 detect-only, 2 online.
-// MMA: the product on v_mfma_f64_16x16x4_f64 instead of SIMT FMAs.  The four
-// wavefronts form a 2 x 2 grid of 64 x 64 sub-tiles (wm = wave & 1 along i,
-// wn = wave >> 1 along j), each 4 x 4 blocks of 16 x 16.  The instruction
-// computes the transposed block P^T = B^T A^T: lane l supplies
-// B[k0 + l / 16][j0 + l % 16] and A[i0 + l % 16][k0 + l / 16] (both one
-// consecutive 16-lane row of the k-major LDS panels) and holds
-// P[i0 + l % 16][j0 + 4 q + l / 16] in component q (the instruction's lane
-// layout, measured on the device), so a lane owns one row of C per block and
-// stores along i are coalesced.
-template <int FT, bool INJ, bool MMA>
+template <int FT, bool INJ>
 __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ty = tid >> 4, tx = tid & 15;
-    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, lg = lane >> 4;   // matrix-core form
+    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, lg = lane >> 4;
     const int i0 = tm * BM, j0 = tn * BN;
     const int mI = min(BM, a.M - i0), nJ = min(BN, a.N - j0);
     const int nk = (a.K + BK - 1) / BK;
     const bool row_owner = tid < BM;
     const int own = row_owner ? tid : tid - BM;   // owned tile row or column
 
-    double acc[MMA ? 1 : TPT][MMA ? 1 : TPT];   // SIMT micro-tile
-    f64x4 accm[MMA ? 4 : 1][MMA ? 4 : 1];        // matrix-core blocks [bj][bi]
-    if constexpr (MMA) {
+    f64x4 accm[4][4];   // matrix-core blocks [bj][bi]
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) accm[bj][bi] = f64x4{0.0, 0.0, 0.0, 0.0};
-    } else {
-#pragma unroll
-        for (int r = 0; r < TPT; ++r)
-#pragma unroll
-            for (int c = 0; c < TPT; ++c) acc[r][c] = 0.0;
-    }
+        for (int bi = 0; bi < 4; ++bi) accm[bj][bi] = f64x4{0.0, 0.0, 0.0, 0.0};
     double ref = 0.0, nrm2 = 0.0;   // R_i or S_j, ||a_i||^2 or ||b_j||^2 over the k prefix
 
     int fnext = 0, flogged = 0;
@@ -236,60 +218,29 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
 
     // ---- online check after k-step t (kp = k indices accumulated) ----
     auto check = [&](int t, int kp) {
-        if constexpr (MMA) {
-            // row sums: a lane's 16 values of a block row, then lane bits 4, 5,
-            // then the two wave columns in LDS; column sums: the four blocks
-            // of a lane's column, then lane bits 0..3, then the two wave rows
+        // row sums: a lane's 16 values of a block row, then lane bits 4, 5,
+        // then the two wave columns in LDS; column sums: the four blocks
+        // of a lane's column, then lane bits 0..3, then the two wave rows
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) {
-                double x = 0.0;
-#pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) x += accm[bj][bi][q];
-                x = swap_sum64<5>(swap_sum64<4>(x));
-                if (lg == 0) s.rowpart[wn][64 * wm + 16 * bi + li] = x;
-            }
+        for (int bi = 0; bi < 4; ++bi) {
+            double x = 0.0;
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    double y = 0.0;
-#pragma unroll
-                    for (int bi = 0; bi < 4; ++bi) y += accm[bj][bi][q];
-                    y = row_sum64(y);
-                    if (li == 0) s.colpart[wm][64 * wn + 16 * bj + 4 * q + lg] = y;
-                }
-        } else {
-            // row sums (over the 16 threads tx of one ty: lane bits 0..3)
-            double rs[TPT], cs[TPT];
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) {
-                double x = 0.0;
-#pragma unroll
-                for (int c = 0; c < TPT; ++c) x += acc[r][c];
-                rs[r] = x;
-            }
-#pragma unroll
-            for (int c = 0; c < TPT; ++c) {
-                double x = 0.0;
-#pragma unroll
-                for (int r = 0; r < TPT; ++r) x += acc[r][c];
-                cs[c] = x;
-            }
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) rs[r] = row_sum64(rs[r]);
-#pragma unroll
-            for (int c = 0; c < TPT; ++c) cs[c] = swap_sum64<5>(swap_sum64<4>(cs[c]));
-            if (tx == 0) {
-#pragma unroll
-                for (int r = 0; r < TPT; ++r) s.rowsum[tile_row(ty, r)] = rs[r];
-            }
-            if ((lane >> 4) == 0) {
-#pragma unroll
-                for (int c = 0; c < TPT; ++c) s.colpart[wave][tile_row(tx, c)] = cs[c];
-            }
+                for (int q = 0; q < 4; ++q) x += accm[bj][bi][q];
+            x = swap_sum64<5>(swap_sum64<4>(x));
+            if (lg == 0) s.rowpart[wn][64 * wm + 16 * bi + li] = x;
         }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double y = 0.0;
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi) y += accm[bj][bi][q];
+                y = row_sum64(y);
+                if (li == 0) s.colpart[wm][64 * wn + 16 * bj + 4 * q + lg] = y;
+            }
         const double nv = sqrt(nrm2);
         const double ws = wave_sum64(nv);
         if (lane == 0) s.nsum[wave] = ws;
@@ -300,7 +251,7 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         // values) non-finite: nothing is flagged and the tile is reported once.
         const bool finite = __builtin_amdgcn_readfirstlane((__builtin_isfinite(sa) && __builtin_isfinite(sb)) ? 1 : 0) != 0;
         if (tid == 0) {
-            atomicAdd(&a.counters[CNT_CHECKS], 1u);
+            s.nchecks += 1u;
             if (!finite && !s.nonfinite) {
                 s.nonfinite = 1;
                 const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
@@ -319,12 +270,11 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         double res = 0.0, tau = 0.0;
         bool flag = false;
         if (finite && row_owner && own < mI) {
-            res = (MMA ? s.rowpart[0][own] + s.rowpart[1][own] : s.rowsum[own]) - ref;
+            res = (s.rowpart[0][own] + s.rowpart[1][own]) - ref;
             tau = base * (double)(kp + nJ + 1) * nv * sb;
             flag = !(fabs(res) <= tau);
         } else if (finite && !row_owner && own < nJ) {
-            res = (MMA ? s.colpart[0][own] + s.colpart[1][own]
-                       : (s.colpart[0][own] + s.colpart[1][own]) + (s.colpart[2][own] + s.colpart[3][own])) - ref;
+            res = (s.colpart[0][own] + s.colpart[1][own]) - ref;
             tau = base * (double)(kp + mI + 1) * nv * sa;
             flag = !(fabs(res) <= tau);
         }
@@ -373,59 +323,36 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             // P_ij = R_i - sum_{j' != j} P_ij'
             double oldv = 0.0, newv = 0.0;
             bool owner = false;
-            if constexpr (MMA) {
-                // row fr: lanes li = fr % 16 of the two waves of wave row fr / 64,
-                // block row (fr % 64) / 16; partials over lane bits 4, 5, then LDS
-                const int fbi = (fr & 63) >> 4, fbj = (fc & 63) >> 4, fq = (fc & 15) >> 2;
-                const bool in_row = wm == (fr >> 6) && li == (fr & 15);
-                owner = in_row && wn == (fc >> 6) && lg == (fc & 3);
-                // (per-lane selects over every element, no branches: branches on the
-                // block index would make the compiler copy the accumulators)
-                double part = 0.0;
+            // row fr: lanes li = fr % 16 of the two waves of wave row fr / 64,
+            // block row (fr % 64) / 16; partials over lane bits 4, 5, then LDS
+            const int fbi = (fr & 63) >> 4, fbj = (fc & 63) >> 4, fq = (fc & 15) >> 2;
+            const bool in_row = wm == (fr >> 6) && li == (fr & 15);
+            owner = in_row && wn == (fc >> 6) && lg == (fc & 3);
+            // (per-lane selects over every element, no branches: branches on the
+            // block index would make the compiler copy the accumulators)
+            double part = 0.0;
 #pragma unroll
-                for (int bi = 0; bi < 4; ++bi)
+            for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const bool mine = in_row && bi == fbi;
-                            const bool hit = owner && bi == fbi && bj == fbj && q == fq;
-                            part += (mine && !hit) ? accm[bj][bi][q] : 0.0;
-                            oldv = hit ? accm[bj][bi][q] : oldv;
-                        }
-                part = swap_sum64<5>(swap_sum64<4>(part));
-                if (wm == (fr >> 6) && lane == (fr & 15)) s.excl[wn] = part;
-                __syncthreads();
-                newv = s.bc[0] - (s.excl[0] + s.excl[1]);
-#pragma unroll
-                for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            accm[bj][bi][q] = (owner && bi == fbi && bj == fbj && q == fq) ? newv : accm[bj][bi][q];
-            } else {
-                // the 16 threads (one ty) holding row fr
-                const int fry = line_owner(fr), frr = line_slot(fr), fcx = line_owner(fc), fcc = line_slot(fc);
-                double part = 0.0;
-                const bool mine_row = ty == fry;
-#pragma unroll
-                for (int r = 0; r < TPT; ++r)
-#pragma unroll
-                    for (int c = 0; c < TPT; ++c) {
-                        const bool in_row = mine_row && r == frr;
-                        const bool hit = in_row && tx == fcx && c == fcc;
-                        part += (in_row && !hit) ? acc[r][c] : 0.0;
-                        oldv = hit ? acc[r][c] : oldv;
+                    for (int q = 0; q < 4; ++q) {
+                        const bool mine = in_row && bi == fbi;
+                        const bool hit = owner && bi == fbi && bj == fbj && q == fq;
+                        part += (mine && !hit) ? accm[bj][bi][q] : 0.0;
+                        oldv = hit ? accm[bj][bi][q] : oldv;
                     }
-                part = row_sum64(part);
-                newv = s.bc[0] - part;
-                owner = mine_row && tx == fcx;
+            part = swap_sum64<5>(swap_sum64<4>(part));
+            if (wm == (fr >> 6) && lane == (fr & 15)) s.excl[wn] = part;
+            __syncthreads();
+            newv = s.bc[0] - (s.excl[0] + s.excl[1]);
 #pragma unroll
-                for (int r = 0; r < TPT; ++r)
+            for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                    for (int c = 0; c < TPT; ++c) acc[r][c] = (owner && r == frr && c == fcc) ? newv : acc[r][c];
-            }
+                for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        accm[bj][bi][q] = (owner && bi == fbi && bj == fbj && q == fq) ? newv : accm[bj][bi][q];
             if (owner) {
                 const unsigned e = atomicAdd(&a.counters[CNT_EVENTS], 1u);
                 atomicAdd(&a.counters[CNT_DETECTED], 1u);
@@ -468,7 +395,7 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
 
     if constexpr (FT > 0) {
         if (tid < 3 * BK) (&s.vsum[0][0])[tid] = 0.0;
-        if (tid == 0) s.nonfinite = 0;
+        if (tid == 0) { s.nonfinite = 0; s.nchecks = 0; }
         __syncthreads();
     }
     load(0);
@@ -479,35 +406,19 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         if (t + 1 < nk) load(t + 1);
         // slot of panel t + 2: its last reader (step t - 1) finished before this step
         if (FT > 0 && t + 2 < nk && tid < BK) s.vsum[(t + 2) % 3][tid] = 0.0;
-        if constexpr (MMA) {
-            // the product of this k-step, four k at a time on the matrix cores
+        // the product of this k-step, four k at a time on the matrix cores
 #pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks) {
-                double bf[4], af[4];
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            double bf[4], af[4];
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) bf[bj] = s.Bs[cur][4 * ks + lg][64 * wn + 16 * bj + li];
+            for (int bj = 0; bj < 4; ++bj) bf[bj] = s.Bs[cur][4 * ks + lg][64 * wn + 16 * bj + li];
 #pragma unroll
-                for (int bi = 0; bi < 4; ++bi) af[bi] = s.As[cur][4 * ks + lg][64 * wm + 16 * bi + li];
+            for (int bi = 0; bi < 4; ++bi) af[bi] = s.As[cur][4 * ks + lg][64 * wm + 16 * bi + li];
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                    for (int bi = 0; bi < 4; ++bi)
-                        accm[bj][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], accm[bj][bi], 0, 0, 0);
-            }
-        } else {
-            // the product of this k-step, one k at a time (outer products)
-#pragma unroll 4
-            for (int k = 0; k < BK; ++k) {
-                double av[TPT], bv[TPT];
-#pragma unroll
-                for (int r = 0; r < TPT; ++r) av[r] = s.As[cur][k][tile_row(ty, r)];
-#pragma unroll
-                for (int c = 0; c < TPT; ++c) bv[c] = s.Bs[cur][k][tile_row(tx, c)];
-#pragma unroll
-                for (int r = 0; r < TPT; ++r)
-#pragma unroll
-                    for (int c = 0; c < TPT; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
-            }
+                for (int bi = 0; bi < 4; ++bi)
+                    accm[bj][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], accm[bj][bi], 0, 0, 0);
         }
         if constexpr (FT > 0) {
             // reference checksums (Eq. 4): R_i += sum_k A[i,k] (B e)[k], S_j += sum_k (e^T A)[k] B[k,j]
@@ -525,38 +436,22 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
                 const ftgemm_fault_t f = s.fault[fnext];
                 bool owner;
                 double oldv = 0.0, newv = 0.0;
-                if constexpr (MMA) {
-                    const int fbi = (f.row & 63) >> 4, fbj = (f.col & 63) >> 4, fq = (f.col & 15) >> 2;
-                    owner = wm == (f.row >> 6) && wn == (f.col >> 6) && li == (f.row & 15) && lg == (f.col & 3);
+                const int fbi = (f.row & 63) >> 4, fbj = (f.col & 63) >> 4, fq = (f.col & 15) >> 2;
+                owner = wm == (f.row >> 6) && wn == (f.col >> 6) && li == (f.row & 15) && lg == (f.col & 3);
 #pragma unroll
-                    for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                        for (int bi = 0; bi < 4; ++bi)
+                    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const bool hit = owner && bj == fbj && bi == fbi && q == fq;
-                                const double x = accm[bj][bi][q];
-                                const double y = f.kind == FTGEMM_FAULT_XOR ? flip64(x, (int)f.payload)
-                                                                            : x + (double)f.payload;
-                                oldv = hit ? x : oldv;
-                                newv = hit ? y : newv;
-                                accm[bj][bi][q] = hit ? y : x;
-                            }
-                } else {
-                    owner = line_owner(f.row) == ty && line_owner(f.col) == tx;
-                    const int fr = line_slot(f.row), fc = line_slot(f.col);
-#pragma unroll
-                    for (int r = 0; r < TPT; ++r)
-#pragma unroll
-                        for (int c = 0; c < TPT; ++c) {
-                            const bool hit = owner && r == fr && c == fc;
-                            const double x = acc[r][c];
-                            const double y = f.kind == FTGEMM_FAULT_XOR ? flip64(x, (int)f.payload) : x + (double)f.payload;
+                        for (int q = 0; q < 4; ++q) {
+                            const bool hit = owner && bj == fbj && bi == fbi && q == fq;
+                            const double x = accm[bj][bi][q];
+                            const double y = f.kind == FTGEMM_FAULT_XOR ? flip64(x, (int)f.payload)
+                                                                        : x + (double)f.payload;
                             oldv = hit ? x : oldv;
                             newv = hit ? y : newv;
-                            acc[r][c] = hit ? y : x;
+                            accm[bj][bi][q] = hit ? y : x;
                         }
-                }
                 if (owner) {
                     const int slot = (int)atomicAdd(&a.counters[CNT_FAULTS], 1u);
                     s.fslot[fnext] = slot;
@@ -580,47 +475,32 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         __syncthreads();
     }
 
+    if (FT > 0 && tid == 0) atomicAdd(&a.counters[CNT_CHECKS], s.nchecks);   // written before the last barrier
+
     // epilogue: C = alpha P + beta C (beta == 0: C is not read)
-    if constexpr (MMA) {
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int j = 64 * wn + 16 * bj + 4 * q + lg;
+        for (int q = 0; q < 4; ++q) {
+            const int j = 64 * wn + 16 * bj + 4 * q + lg;
 #pragma unroll
-                for (int bi = 0; bi < 4; ++bi) {
-                    const int i = 64 * wm + 16 * bi + li;
-                    if (i < mI && j < nJ) {
-                        double* pc = a.C + (size_t)(j0 + j) * a.ldc + (i0 + i);
-                        double v = a.alpha * accm[bj][bi][q];
-                        if (a.beta != 0.0) v = fma(a.beta, *pc, v);
-                        *pc = v;
-                    }
-                }
-            }
-    } else {
-#pragma unroll
-        for (int c = 0; c < TPT; ++c) {
-            const int j = tile_row(tx, c);
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) {
-                const int i = tile_row(ty, r);
+            for (int bi = 0; bi < 4; ++bi) {
+                const int i = 64 * wm + 16 * bi + li;
                 if (i < mI && j < nJ) {
                     double* pc = a.C + (size_t)(j0 + j) * a.ldc + (i0 + i);
-                    double v = a.alpha * acc[r][c];
+                    double v = a.alpha * accm[bj][bi][q];
                     if (a.beta != 0.0) v = fma(a.beta, *pc, v);
                     *pc = v;
                 }
             }
         }
-    }
 }
 
-template <int FT, bool INJ, bool MMA>
+template <int FT, bool INJ>
 __global__ __launch_bounds__(NT, 2) void ftgemm_f64_kernel(F64Args a) {
     __shared__ F64Lds s;
     const int ntm = (a.M + BM - 1) / BM;
-    tile64<FT, INJ, MMA>(a, blockIdx.x % ntm, blockIdx.x / ntm, s);
+    tile64<FT, INJ>(a, blockIdx.x % ntm, blockIdx.x / ntm, s);
 }
 
 __global__ void scale64_kernel(double* C, int64_t ldc, int32_t M, int32_t N, double beta) {
@@ -631,9 +511,6 @@ __global__ void scale64_kernel(double* C, int64_t ldc, int32_t M, int32_t N, dou
         *p = (beta == 0.0) ? 0.0 : beta * *p;
     }
 }
-
-// The product on the matrix cores (v_mfma_f64_16x16x4_f64) or as SIMT FMAs.
-constexpr bool kF64Mma = true;
 
 constexpr Variant kVariantsF64[] = {
     {BM, BN, BK, BM, BN},
@@ -657,7 +534,7 @@ hipError_t launch_fp64(int idx, bool inject, const F64Args& a, hipStream_t s) {
     if (idx != 0) return hipErrorInvalidValue;
     const int ntm = (a.M + BM - 1) / BM, ntn = (a.N + BN - 1) / BN;
     const dim3 grid((unsigned)(ntm * ntn)), block(NT);
-#define FTGEMM_LAUNCH(FTL, INJL) hipLaunchKernelGGL((ftgemm_f64_kernel<FTL, INJL, kF64Mma>), grid, block, 0, s, a)
+#define FTGEMM_LAUNCH(FTL, INJL) hipLaunchKernelGGL((ftgemm_f64_kernel<FTL, INJL>), grid, block, 0, s, a)
     if (inject) {
         if (a.ft_level == 0) FTGEMM_LAUNCH(0, true);
         else if (a.ft_level == 1) FTGEMM_LAUNCH(1, true);

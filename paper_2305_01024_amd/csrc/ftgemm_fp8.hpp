@@ -88,7 +88,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
 
     if constexpr (FT > 0) {
         for (int x = tid; x < 3 * BK; x += NT) (&op.vsum[0][0])[x] = 0.f;
-        if (tid == 0) { sm.ck.tainted = 0; sm.ck.nonfinite = 0; }
+        if (tid == 0) { sm.ck.tainted = 0; sm.ck.nonfinite = 0; sm.ck.nchecks = 0; }
     }
     int fnext = 0, flogged = 0;
     if constexpr (INJ) gather_faults<G>(sm.ck, a, th);
