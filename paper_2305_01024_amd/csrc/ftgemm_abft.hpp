@@ -148,17 +148,20 @@ struct Thread {
     int tm, tn, i0, j0, mI, nJ;
 };
 
-template <class G>
+// UNIFORM: the wavefront index and what derives from it are computed as
+// wave-uniform values, so scalar registers hold them (the FT kernels, whose
+// vector registers are full; the plain kernels schedule better without it).
+template <class G, bool UNIFORM = false>
 __device__ __forceinline__ Thread make_thread(const LaunchArgs& a, int tm, int tn) {
     Thread t;
     t.tid = threadIdx.x;
     t.lane = t.tid & 63;
-    t.wave = t.tid >> 6;
+    const int wave_u = __builtin_amdgcn_readfirstlane(t.tid >> 6);
+    t.wave = UNIFORM ? wave_u : t.tid >> 6;
     t.wm = t.wave % G::WM;
     t.wn = t.wave / G::WM;
     t.l32 = t.lane & 31;
     t.hh = t.lane >> 5;
-    const int wave_u = __builtin_amdgcn_readfirstlane(t.wave);
     t.row_role = !G::SPLIT || wave_u < G::BM / 64;
     t.my_row = (t.row_role && t.tid < G::BM) ? t.tid : -1;
     t.my_col = G::SPLIT ? ((!t.row_role && t.tid < G::COL0 + G::BN) ? t.tid - G::COL0 : -1)
@@ -372,10 +375,21 @@ __device__ __forceinline__ void log_nonfinite(const LaunchArgs& a, int tile_m, i
     }
 }
 
+// The per-lane indices, passed through an empty asm at the start of a check:
+// the addresses the check derives from them are then computed inside it
+// rather than hoisted out of the k-loop, where they would hold registers (or
+// spill slots, reloaded at every check) for the whole loop.
+__device__ __forceinline__ Thread opaque_lanes(const Thread& th) {
+    Thread t = th;
+    asm volatile("" : "+v"(t.tid), "+v"(t.lane), "+v"(t.l32), "+v"(t.hh), "+v"(t.my_row), "+v"(t.my_col));
+    return t;
+}
+
 template <class G, int FT, bool INJ>
-__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th, int t, int kp,
+__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th_loop, int t, int kp,
                       float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
     constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
+    const Thread th = opaque_lanes(th_loop);
     const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
 
     // (1) row sums per wave column and column sums per wave row
@@ -394,7 +408,9 @@ __device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Th
     // An Inf or NaN operand in the k prefix makes the norm sums (uniform
     // values) non-finite: nothing is flagged and the tile is reported once.
     const bool finite = __builtin_amdgcn_readfirstlane((__builtin_isfinite(sa) && __builtin_isfinite(sb)) ? 1 : 0) != 0;
-    const float base = a.tol_c * 2.0f * kUnitRoundoff;
+    // uniform: kept in a scalar register
+    const float base = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                     __builtin_bit_cast(int, a.tol_c * 2.0f * kUnitRoundoff)));
     float rres = 0.f, cres = 0.f, taur = 0.f, tauc = 0.f;
     bool rf = false, cf = false;
     if (finite && th.my_row >= 0 && th.my_row < th.mI) {

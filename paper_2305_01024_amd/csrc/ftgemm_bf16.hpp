@@ -84,7 +84,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
 
     OperandsBF16<BM, BN, BK>& op = sm.op;
 
-    const Thread th = make_thread<G>(a, tm, tn);
+    const Thread th = make_thread<G, (FT > 0)>(a, tm, tn);
     const int tid = th.tid, lane = th.lane, wm = th.wm, wn = th.wn, l32 = th.l32, hh = th.hh;
     const int mI = th.mI, nJ = th.nJ;
     const int nk = (a.K + BK - 1) / BK;

@@ -118,7 +118,8 @@ __device__ __forceinline__ double flip64(double v, int bit) {
 // One 128 x 128 tile (tm, tn).  FT: 0 plain, 1 detect-only, 2 online.
 template <int FT, bool INJ>
 __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wavefront index is uniform: scalar registers hold it and what is derived from it
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave & 1, wn = wave >> 1, li = lane & 15, lg = lane >> 4;
     const int i0 = tm * BM, j0 = tn * BN;
     const int mI = min(BM, a.M - i0), nJ = min(BN, a.N - j0);
