@@ -33,9 +33,8 @@ struct alignas(16) OperandsFP8 {   // 16-byte aligned: the panel reads are 16-by
     static constexpr int KP = BK + 16;         // row pitch in bytes (16 B of padding)
     unsigned char As[2][BM][KP];               // A panel, i-major, k contiguous
     unsigned char Bs[2][BN][KP];               // B panel, j-major, k contiguous
-    float wsum[2][BK];                         // e^T A per k
+    float wsum[3][BK];                         // e^T A per k (accumulated across waves, 3 rotating slots)
     float vsum[3][BK];                         // B e per k (accumulated across waves, 3 rotating slots)
-    float dummy[64];
 };
 
 template <int BM, int BN, int BK, int WM, int WN>
@@ -62,15 +61,20 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     using G = Geometry<BM, BN, WM, WN>;
     constexpr int NT = G::NT, TM = G::TM, TN = G::TN, MI = G::MI, NI = G::NI;
     constexpr int KP = OperandsFP8<BM, BN, BK>::KP;
-    // A: an 8-row x 4-k block per thread (rows 8 ac.., k 4 akq..), with the
-    // 32 lanes of one k-quad covering 256 contiguous rows.  B: 16-byte
-    // k-chunks (16 k of one column).
+    // A: an 8-row x 4-k block per thread (rows 8 ac.., k 4 akq..), the 16
+    // k-quads of the panel on consecutive lanes.  The transposed stores of a
+    // block go to 8 rows 8 ac + r; rows 8 apart are 640 bytes apart, the same
+    // LDS bank, so lanes with different ac but the same k-quad would all
+    // write one bank.  With the k-quad on the low lane bits the 16 lanes of a
+    // store group write 16 consecutive dwords of one row (no conflict).  A
+    // global load of a wave then reads 32 contiguous bytes of each of 16
+    // columns.  B: 16-byte k-chunks (16 k of one column).
     constexpr int ARB = BM / 8;                 // row blocks of the A panel
     constexpr int AKQ = BK / 4;                 // k-quads per panel
     constexpr int BKC = BK / 16;                // k-chunks per column
     constexpr int NB = BN * BKC / NT;           // B chunks per thread
     static_assert(G::SPLIT, "the fp8 kernel assumes one owned row or column per thread");
-    static_assert(ARB * AKQ == NT && ARB == 32, "one A block per thread, 32 lanes per k-quad");
+    static_assert(ARB * AKQ == NT && AKQ == 16, "one A block per thread, the 16 k-quads on lane bits 0-3");
     static_assert(NB >= 1 && NT % BKC == 0 && BK % 16 == 0 && BKC == 4, "B chunk mapping");
     static_assert(BM == BN, "owner addressing assumes square tiles");
 
@@ -87,7 +91,10 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     const bool alignB = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && ((a.ldb & 15) == 0);
 
     if constexpr (FT > 0) {
-        for (int x = tid; x < 3 * BK; x += NT) (&op.vsum[0][0])[x] = 0.f;
+        for (int x = tid; x < 3 * BK; x += NT) {
+            (&op.wsum[0][0])[x] = 0.f;
+            (&op.vsum[0][0])[x] = 0.f;
+        }
         if (tid == 0) { sm.ck.tainted = 0; sm.ck.nonfinite = 0; sm.ck.nchecks = 0; }
     }
     int fnext = 0, flogged = 0;
@@ -95,9 +102,13 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     __syncthreads();
 
     // ---- global -> register staging ----
-    const int ac = tid % ARB, akq = tid / ARB;     // A block: rows 8 ac.., k 4 akq..
-    u32x2 ra[4];                                    // 4 k-columns x 8 rows (bytes)
-    u32x4 rb[NB];                                   // 16 k of one column each
+    // The plain kernel keeps two staging sets and loads two k-steps ahead: a
+    // 64-k FP8 step is too short to cover the global load latency with one.
+    // The FT kernels have no registers for a second set.
+    constexpr int NS = FT == 0 ? 2 : 1;
+    const int akq = tid % AKQ, ac = tid / AKQ;     // A block: rows 8 ac.., k 4 akq..
+    u32x2 ras[NS][4];                               // 4 k-columns x 8 rows (bytes)
+    u32x4 rbs[NS][NB];                              // 16 k of one column each
     const unsigned char* Abase = A + th.i0;
     const unsigned char* Bbase = B + (size_t)th.j0 * a.ldb;
 
@@ -115,7 +126,9 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     }
     constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
 
-    auto load_panels = [&](int t) {
+    auto load_panels = [&](int t, auto set) {
+        u32x2* ra = ras[decltype(set)::value];
+        u32x4* rb = rbs[decltype(set)::value];
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
         // the edge paths take their k origin through an empty asm so that the
@@ -174,7 +187,9 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
 
     // registers -> LDS (A transposed to k-contiguous rows), fused with the
     // encodings e^T A and B e in FP32 (section 2.2, Eq. 1-2)
-    auto store_panels = [&](int buf, int slot) {
+    auto store_panels = [&](int buf, int slot, auto set) {
+        const u32x2* ra = ras[decltype(set)::value];
+        const u32x4* rb = rbs[decltype(set)::value];
         // column e of the block holds rows 8 ac .. 8 ac + 7 as bytes; row r
         // gathers byte r of the 4 columns into one dword (k 4 akq .. +3).
 #pragma unroll
@@ -191,9 +206,10 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][16 * kc]) = rb[r];
         }
         if constexpr (FT > 0) {
-            // e^T A for the thread's 4 k over its 8 rows, then over the 32
-            // lanes of the same k-quad (bits 0..4): the reduce-scatter leaves
-            // k = 4 akq + ((lane >> 3) & 3), stored by lanes with (lane & 7) == 0.
+            // e^T A for the thread's 4 k over its 8 rows, then over the 4
+            // lanes of the same k-quad in the wave (bits 4, 5): the
+            // reduce-scatter leaves k = 4 akq + ((lane >> 4) & 3); waves add
+            // in LDS.
             float ws[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -202,11 +218,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
                 decode4(ra[e][1], f1);
                 ws[e] = ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f1[0] + f1[1]) + (f1[2] + f1[3]));
             }
-            ReduceScatter<4, 4, 0>::run(ws, lane);
-            {
-                float* dst = ((lane & 7) == 0) ? &op.wsum[buf][4 * akq + ((lane >> 3) & 3)] : &op.dummy[lane];
-                *dst = ws[0];
-            }
+            ReduceScatter<4, 5, 4>::run(ws, lane);
+            atomicAdd(&op.wsum[slot][4 * akq + ((lane >> 4) & 3)], ws[0]);
             // B e for the thread's 16 k over its NB columns, then over the
             // lanes of the same k-chunk (bits 2..5): lane keeps
             // k = 16 kc + ((lane >> 2) & 15); waves add in LDS.
@@ -278,7 +291,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     // reference checksum update (Eq. 4) for the same 16 k
     auto ft_sub = [&](int cur, int slot, int s) {
         const unsigned char* px = x_arr + cur * XBUF + own * KP + 16 * s;
-        const float* py = row_role ? &op.vsum[slot][16 * s] : &op.wsum[cur][16 * s];
+        const float* py = row_role ? &op.vsum[slot][16 * s] : &op.wsum[slot][16 * s];
         const u32x4 xv = *reinterpret_cast<const u32x4*>(px);
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
@@ -293,19 +306,31 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         }
     };
 
-    auto step = [&](int t, auto has_next) {
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, NS - 1>;
+    // One k-step.  NEXT: store the staged panels of step t + 1 (set `held`).
+    // FT kernels load step t + 1 into their one set first; the plain kernel
+    // loads step t + 2 (if any) into the other set.
+    auto step = [&](int t, auto has_next, auto held) {
         constexpr bool NEXT = decltype(has_next)::value;
+        constexpr int H = decltype(held)::value;
         const int cur = t & 1;
-        if constexpr (NEXT) load_panels(t + 1);
+        if constexpr (NS == 1) {
+            if constexpr (NEXT) load_panels(t + 1, S0{});
+        } else {
+            if (t + 2 < nk) load_panels(t + 2, std::integral_constant<int, 1 - H>{});
+        }
         if constexpr (FT > 0 && NEXT) {   // slot for step t+2: its last reader finished before this step
-            (&op.vsum[(t + 2) % 3][0])[tid < BK ? tid : BK - 1] = 0.f;
+            const int x = tid < BK ? tid : BK - 1;
+            op.wsum[(t + 2) % 3][x] = 0.f;
+            op.vsum[(t + 2) % 3][x] = 0.f;
         }
 #pragma unroll
         for (int s = 0; s < BK / 16; ++s) {
             mfma_sub(cur, s);
             if constexpr (FT > 0) ft_sub(cur, t % 3, s);
             if constexpr (NEXT) {
-                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3);
+                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3, held);
             }
         }
     };
@@ -321,14 +346,33 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         return do_check;
     };
 
-    load_panels(0);
-    store_panels(0, 0);
-    __syncthreads();
-    for (int t = 0; t + 1 < nk; ++t) {
-        step(t, std::true_type{});
-        if (!post(t)) __syncthreads();
+    load_panels(0, S0{});
+    store_panels(0, 0, S0{});
+    if constexpr (NS == 2) {
+        if (nk > 1) load_panels(1, S1{});
     }
-    step(nk - 1, std::false_type{});
+    __syncthreads();
+    int t = 0;
+    if constexpr (NS == 1) {
+        for (; t + 1 < nk; ++t) {
+            step(t, std::true_type{}, S0{});
+            if (!post(t)) __syncthreads();
+        }
+    } else {
+        // steps in pairs, so that each step's staging set is a compile-time index
+        for (; t + 2 < nk; t += 2) {
+            step(t, std::true_type{}, S1{});
+            if (!post(t)) __syncthreads();
+            step(t + 1, std::true_type{}, S0{});
+            if (!post(t + 1)) __syncthreads();
+        }
+        if (t + 1 < nk) {
+            step(t, std::true_type{}, S1{});
+            if (!post(t)) __syncthreads();
+            ++t;
+        }
+    }
+    step(nk - 1, std::false_type{}, S0{});
     post(nk - 1);
     finish_tile<G, FT>(acc, sm.ck, a, th, a.scale);
 }
