@@ -136,9 +136,9 @@ double modelled_time(const Variant& x, const VariantModel& mdl, int64_t m, int64
     return t;
 }
 
-// FP32 and BF16: the compute-tile variant with the least modelled time (ties:
-// the earlier, larger tile); FP8 and FP64: their one variant.  A check every
-// 256 k.
+// FP32, BF16 and FP8: the compute-tile variant with the least modelled time
+// (ties: the earlier, larger tile); FP64 and double complex: their one
+// variant.  A check every 256 k.
 int select_variant(int dtype, int64_t m, int64_t n, int ft_level, ftgemm_config_t* out) {
     const int nv = variant_count(dtype);
     int pick = -1;
@@ -146,11 +146,13 @@ int select_variant(int dtype, int64_t m, int64_t n, int ft_level, ftgemm_config_
     for (int v = 0; v < nv; ++v) {
         const Variant x = variant_at(dtype, v);
         if (!compute_tile_check(x)) continue;
-        if (dtype != FTGEMM_F32 && dtype != FTGEMM_BF16) {
+        if (dtype != FTGEMM_F32 && dtype != FTGEMM_BF16 && dtype != FTGEMM_F8E4M3) {
             pick = v;
             break;
         }
-        const VariantModel mdl = dtype == FTGEMM_BF16 ? bf16_variant_model(v) : fp32_variant_model(v);
+        const VariantModel mdl = dtype == FTGEMM_BF16     ? bf16_variant_model(v)
+                                 : dtype == FTGEMM_F8E4M3 ? fp8_variant_model(v)
+                                                          : fp32_variant_model(v);
         const double t = modelled_time(x, mdl, std::max<int64_t>(m, 1), std::max<int64_t>(n, 1),
                                        base_level(ft_level) > 0);
         if (pick < 0 || t < best * (1.0 - 1e-9)) {

@@ -264,10 +264,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     // (E4M3 operands, unit block scales): lane l supplies 32 consecutive k
     // (32 bytes, two 16-byte LDS reads) of one row, the lane halves taking
     // k 0..31 and 32..63.  Both operands are read with the same lane -> k
-    // assignment, so every product pairs a_ik with b_kj.  Sub-step s issues
-    // the MFMAs of row block s; the column-block fragments are read at s = 0
-    // and kept for the step.
-    static_assert(MI == BK / 16 && BK == 64, "one row block per sub-step, one MFMA per block per step");
+    // assignment, so every product pairs a_ik with b_kj.  The step has four
+    // sub-steps of 16 k for the checksum update; sub-step s issues the MFMAs
+    // of row block s (none when the wavefront has fewer than s + 1 row
+    // blocks); the column-block fragments are read at s = 0 and kept for the
+    // step.
+    static_assert(MI <= BK / 16 && BK == 64, "at most one row block per sub-step, one MFMA per block per step");
     typedef int i32x8 __attribute__((ext_vector_type(8)));
     constexpr int kScaleOne = 127;   // E8M0 block scale 2^0
     i32x8 bxk[NI];
@@ -327,7 +329,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         }
 #pragma unroll
         for (int s = 0; s < BK / 16; ++s) {
-            mfma_sub(cur, s);
+            if (s < MI) mfma_sub(cur, s);
             if constexpr (FT > 0) ft_sub(cur, t % 3, s);
             if constexpr (NEXT) {
                 if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3, held);

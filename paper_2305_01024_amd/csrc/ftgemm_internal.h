@@ -92,6 +92,7 @@ hipError_t launch_bf16_retry(int idx, const LaunchArgs& a, int grid, hipStream_t
 // Kernel variants for FP8 E4M3 operands (A, B as 8-bit codes).
 int fp8_variant_count();
 Variant fp8_variant(int idx);
+VariantModel fp8_variant_model(int idx);
 int fp8_find_variant(int m_tile, int n_tile, int k_step, int check_m, int check_n);
 hipError_t launch_fp8(int idx, bool inject, const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_fp8_retry(int idx, const LaunchArgs& a, int grid, hipStream_t stream);

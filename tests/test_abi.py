@@ -184,6 +184,13 @@ def test_select_config_follows_the_measured_best_tile_and_checks_every_256_k():
         for level in (F.FT_OFF, F.FT_CORRECT):
             c = F.ftgemm_select_config(F.BF16, N, N, N, level)
             assert (c.m_tile, c.n_tile, c.k_step * c.check_interval) == (t, t, 256), (N, level, c.as_tuple())
+    # FP8, the same model with the FP8 tiles' measured rates: 128 x 128 up to
+    # 2560^3 (2048^3 online: 0.090 against 0.145 ms), 256 x 256 from 3072^3
+    # (0.209 against 0.273 ms)
+    for N, t in {1024: 128, 2048: 128, 2560: 128, 3072: 256, 4096: 256, 8192: 256}.items():
+        for level in (F.FT_OFF, F.FT_CORRECT):
+            c = F.ftgemm_select_config(F.F8E4M3, N, N, N, level)
+            assert (c.m_tile, c.n_tile, c.k_step * c.check_interval) == (t, t, 256), (N, level, c.as_tuple())
     # FP64: the one compiled configuration, a check every 256 k, for any shape and level
     for (m, n) in [(8192, 8192), (1, 1), (3001, 1999)]:
         for level in (F.FT_OFF, F.FT_DETECT, F.FT_CORRECT):
