@@ -390,6 +390,7 @@ def bench_batched(args):
     probs = F.make_problems(len(shapes))
     keep = []
     flop = 0.0
+    t_peak = 0.0   # the batch's time at the dense peak of each problem's operand type, seconds
     for p, b in enumerate(shapes):
         A = torch.randn(b.k, b.m, device="cuda", generator=gen)        # column-major m x k
         B = torch.randn(b.n, b.k, device="cuda", generator=gen)        # column-major k x n
@@ -405,6 +406,7 @@ def bench_batched(args):
         q["alpha"], q["beta"], q["scale_a"], q["scale_b"] = 1.0, 0.0, 1.0, 1.0
         q["A"], q["B"], q["C"] = A.data_ptr(), B.data_ptr(), C.data_ptr()
         flop += 2.0 * b.m * b.n * b.k
+        t_peak += 2.0 * b.m * b.n * b.k / ((PEAK_BF16_MFMA_TFLOPS if b.dtype == "bf16" else PEAK_FP32_MFMA_TFLOPS) * 1e12)
     stream = torch.cuda.current_stream()
     h = F.ftgemm_create(F.F32, 0)
     hb = F.ftgemm_create(F.BF16, 0)
@@ -469,7 +471,11 @@ def bench_batched(args):
            "variant_rates_mac_per_s": [float(r) for r in rates],
            "injection": {"injected": int(len(flog)), "corrected_at_site": int(hit),
                          "events": int(rep.report.n_events), "uncorrectable": int(rep.report.uncorrectable)},
-           "roofline": None, "cpu_baseline": None}, args)
+           # the mix's peak: its FLOPs over the time they take at each problem's dense MFMA peak
+           "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": round(flop / t_peak / 1e12, 1),
+                        "unit": "TFLOP/s", "frac": round(tf / (flop / t_peak / 1e12), 4), "traffic": None,
+                        "peak_note": "FP32 and BF16 dense MFMA peaks weighted by each problem's FLOPs"},
+           "cpu_baseline": None}, args)
 
 
 def bench_irregular(args):
@@ -532,7 +538,12 @@ def bench_irregular(args):
     _line(total_flop / (total_ms * 1e-3) / 1e12, total_ms, "TFLOP/s", "f32",
           {"workload": "FP32 irregular FT-GEMM shapes (65536,256,4096), (256,65536,4096), (16384,16384,64), "
                        "(3001,1999,4097), U[-1,1], beta=0, autotuned configuration, one call per shape per step"},
-          {"shapes": rows, "roofline": None, "cpu_baseline": None}, args)
+          {"shapes": rows,
+           "roofline": {"bound": "mfma", "achieved": round(total_flop / (total_ms * 1e-3) / 1e12, 3),
+                        "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(total_flop / (total_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                        "traffic": None},
+           "cpu_baseline": None}, args)
 
 
 def bench_ablation(args):
