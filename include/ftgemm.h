@@ -259,11 +259,13 @@ int ftgemm_run_noalloc(int dtype, int64_t m, int64_t n, int64_t k, float alpha, 
  * are double, column-major, device pointers as in ftgemm_run; products,
  * accumulation, encodings, reference checksums and the check are binary64,
  * and the threshold takes u = 2^-53 (section 6 names further data types,
- * double-precision complex among them, as future work).  One compiled configuration: 128 x 128 tiles,
+ * double-precision complex among them, as future work).  The products run on
+ * the FP64 matrix cores.  One compiled configuration: 128 x 128 tiles,
  * k-step 16, a check every 16 k-steps (256 k) unless a configuration is
  * forced; ft_level 0, 1 or 2 (FTGEMM_FT_RECOMPUTE is not supported:
  * FTGEMM_UNSUPPORTED).  tol <= 0 selects c = 2.  Events and the fault log
- * carry their values rounded to float.  Injected FTGEMM_FAULT_XOR sites flip
+ * carry their values rounded to float; the fault log also carries the applied
+ * offset `delta` in binary64.  Injected FTGEMM_FAULT_XOR sites flip
  * bit (int)payload of the 64-bit value (0..63).  Same return codes, report
  * and bad_arg positions as ftgemm_run. */
 int ftgemm_run_f64(ftgemm_t handle, int64_t m, int64_t n, int64_t k, double alpha,
