@@ -17,8 +17,8 @@
  *     single-event-upset model of section 4.1) is located at the intersection
  *     of the offending row and column and corrected from the checksum
  *     (section 4.2.1, section 5.3).
- * The detection threshold, which the paper leaves as "a predetermined
- * threshold", is the analytic FP32 roundoff bound
+ * The detection threshold, which the paper fixes in advance without a value
+ * (section 2.2), is the analytic FP32 roundoff bound
  *     tau_row_i = c * 2u (K' + n_J + 1) * ||a_i[0:K']|| * sum_{j in J} ||b_j[0:K']||
  *     tau_col_j = c * 2u (K' + m_I + 1) * ||b_j[0:K']|| * sum_{i in I} ||a_i[0:K']||
  * with u = 2^-24, K' the k indices accumulated so far, (m_I, n_J) the valid

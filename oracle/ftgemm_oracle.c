@@ -19,8 +19,8 @@
  *   - location of a single error at the intersection of the offending row
  *     and column and its correction from the checksum (section 4.2.1 and
  *     section 5.3).
- * The paper leaves the detection threshold unstated ("a predetermined
- * threshold", section 2.2).  The oracle uses the analytic roundoff bound
+ * The paper leaves the detection threshold unstated (section 2.2 fixes it in
+ * advance without a value).  The oracle uses the analytic roundoff bound
  *   beta_row_i = 2u (K' + n_J + 1) ||a_i[0:K']||_2 * sum_{j in J} ||b_j[0:K']||_2
  *   beta_col_j = 2u (K' + m_I + 1) ||b_j[0:K']||_2 * sum_{i in I} ||a_i[0:K']||_2
  * with tau = c * beta, u the unit roundoff of the modelled GPU arithmetic and

@@ -1,6 +1,6 @@
 """Measured margin of the detection threshold on the GPU.
 
-The paper leaves the threshold as a predetermined constant (section 2.2); the
+The paper leaves the threshold as a constant fixed in advance (section 2.2); the
 library uses the analytic roundoff bound beta of the oracle (tau = c * beta,
 c = 2 by default).  Two measurements per operand type, on clean 8192^3 runs
 in the benchmarked configuration:
