@@ -133,6 +133,12 @@ def replay_against_gpu(A, B, cfg, rep, log, C0=None, alpha=1.0, beta=0.0, ft_lev
 
 
 U32 = 2.0 ** -24      # unit roundoff of binary32
+# Accumulation model of the FP8 matrix instruction for element-wise bounds:
+# it sums its 64 products per instruction below binary32 precision (measured
+# on clean N(0,1) data at K = 64, one instruction: |C - AB|_ij up to 2.6e-5
+# (|A||B|)_ij, 1.6 times (k + 2) 2^-22), so the element-wise bound takes
+# u = 2^-19 for it, a factor of about 5 above that measurement.
+U_FP8_ACC = 2.0 ** -19
 
 
 def _abs_product(A, B):

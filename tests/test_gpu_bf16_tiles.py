@@ -1,7 +1,9 @@
 """GPU tests of the BF16 128 x 128 tile (the one automatic selection picks
 below 3072^3): clean runs and an exact injection site log against the oracle
 on the exactly decoded operands.  Bar as for the 256 x 256 BF16 tile: the
-FP32-accumulated product within 1e-5 (relative Frobenius) of the oracle's."""
+FP32-accumulated product within 1e-5 (relative Frobenius) of the oracle's,
+and element by element within (k + 2) 2^-24 (|A||B|)_ij (bf16 products are
+exact, the accumulation binary32)."""
 import numpy as np
 import pytest
 
@@ -9,7 +11,7 @@ from oracle import oracle as O
 from paper_2305_01024_amd import ftgemm as F
 from paper_2305_01024_amd import workloads as W
 
-from gpu_util import event_keys, rel_fro, replay_against_gpu
+from gpu_util import elementwise_ratio, event_keys, rel_fro, replay_against_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -60,7 +62,9 @@ def test_clean_matches_oracle(h, shape):
     st, C, rep, _ = _run(h, Ac, Bc, sa, sb)
     assert st == F.OK and rep.report.n_events == 0
     assert rep.report.config.as_tuple() == CFG + CFG[:2]
-    assert rel_fro(C, O.gemm(A, B, alpha=sa * sb)) <= TOL
+    ref = O.gemm(A, B, alpha=sa * sb)
+    assert rel_fro(C, ref) <= TOL
+    assert elementwise_ratio(C, ref, A, B, alpha=sa * sb) <= 1.0
 
 
 def test_fault_injection_exact_site_log(h):
@@ -74,3 +78,5 @@ def test_fault_injection_exact_site_log(h):
     assert st == F.OK and rep.report.corrected == 12
     assert event_keys(rep.events) == event_keys(res.events)
     assert rel_fro(C, O.gemm(A, B, alpha=sa * sb)) <= TOL
+    assert elementwise_ratio(C, res.C, A, B, CFG, alpha=sa * sb, events=rep.events, oracle_events=res.events,
+                             log=log) <= 1.0

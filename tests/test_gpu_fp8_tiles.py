@@ -1,10 +1,8 @@
 """GPU tests of the FP8 E4M3 128 x 128 tile (the one automatic selection picks
 for smaller problems): clean runs, plain and online, and an exact injection
 site log against the oracle on the exactly decoded operands, element by
-element.  Per-element bound: (k + 2) u (|A||B|)_ij with u = 2^-22 for the
-FP8 matrix instruction, which sums its 64 products per instruction below
-binary32 precision (the relative Frobenius error measured at K = 64 is
-1.5e-5, about 0.75 of the binary32 bound; 2^-22 leaves a factor 4)."""
+element.  Per-element bound: (k + 2) u (|A||B|)_ij with the FP8 matrix
+instruction's accumulation model u = gpu_util.U_FP8_ACC."""
 import numpy as np
 import pytest
 
@@ -12,11 +10,10 @@ from oracle import oracle as O
 from paper_2305_01024_amd import ftgemm as F
 from paper_2305_01024_amd import workloads as W
 
-from gpu_util import elementwise_ratio, event_keys, replay_against_gpu
+from gpu_util import U_FP8_ACC, elementwise_ratio, event_keys, replay_against_gpu
 
 pytestmark = pytest.mark.gpu
 CFG = (128, 128, 64, 4)
-U_FP8_ACC = 2.0 ** -22
 
 
 @pytest.fixture(scope="module")

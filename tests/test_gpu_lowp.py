@@ -14,7 +14,7 @@ from oracle import oracle as O
 from paper_2305_01024_amd import ftgemm as F
 from paper_2305_01024_amd import workloads as W
 
-from gpu_util import event_keys, rel_fro, replay_against_gpu
+from gpu_util import U_FP8_ACC, elementwise_ratio, event_keys, rel_fro, replay_against_gpu
 
 pytestmark = pytest.mark.gpu
 TOL_LOWP = 2e-2
@@ -23,6 +23,10 @@ TOL_LOWP = 2e-2
 # products per instruction at less than FP32 precision (measured 1.5e-5 at
 # K = 64), so its accumulation check is 1e-4.
 TOL_ACC = {"bf16": 1e-5, "fp8": 1e-4}
+# Element-wise bound (k + 2) u (|A||B|)_ij of gpu_util.elementwise_ratio: u =
+# 2^-24 for BF16 (exact products, binary32 accumulation); for FP8 the model
+# of its instruction's accumulation (gpu_util.U_FP8_ACC).
+ACC_U = {"bf16": 2.0 ** -24, "fp8": U_FP8_ACC}
 
 DTYPES = {
     "bf16": (F.BF16, W.quantize_bf16, O.decode_bf16, np.int16, "bf16"),
@@ -92,12 +96,15 @@ def test_clean_matches_oracle(h, shape):
     err = rel_fro(C, ref)
     assert err <= TOL_LOWP
     assert err <= TOL_ACC[h[1][4]], err
+    assert elementwise_ratio(C, ref, A, B, alpha=sa * sb, acc_u=ACC_U[h[1][4]]) <= 1.0
 
 
-@pytest.mark.parametrize("shape", [(512, 768, 640), (300, 520, 200), (1000, 37, 999)])
+@pytest.mark.parametrize("shape", [(512, 768, 640), (300, 520, 200), (1000, 37, 999), (200, 136, 100),
+                                   (136, 200, 190), (64, 64, 1)])
 def test_plain_level_matches_oracle(h, shape):
     """ft_level 0 (the plain kernel, FT compiled out): same bar on the product,
-    no event, including ragged tiles and a partial last k-step."""
+    no event, including ragged tiles and a partial last k-step; 1, 2 and 3
+    k-steps cover the ends of the FP8 plain kernel's two-step-ahead loads."""
     m, n, k = shape
     Ac, sa = _quant(h[1], W.normal((m, k), 301, 0))
     Bc, sb = _quant(h[1], W.normal((k, n), 301, 1))
@@ -185,6 +192,8 @@ def test_fault_injection_exact_site_log(h, kind):
     assert rep.report.corrected >= must and (kind == W.KIND_XOR or must == 20)
     assert event_keys(rep.events) == event_keys(res.events)
     assert rel_fro(C, res.C) <= TOL_ACC[h[1][4]]
+    assert elementwise_ratio(C, res.C, A, B, cfg, events=rep.events, oracle_events=res.events, log=log,
+                             acc_u=ACC_U[h[1][4]]) <= 1.0
 
 
 @functools.lru_cache(maxsize=1)
@@ -213,15 +222,17 @@ def test_full_size_8192_sampled_tiles(h):
     for (tm, tn) in tiles:
         sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
         assert rel_fro(C[sl], res.C[sl]) <= TOL_ACC[h[1][4]], (tm, tn)
+        assert elementwise_ratio(C, res.C, A, B, cfg, alpha=sa * sb, tile=(tm, tn), acc_u=ACC_U[h[1][4]]) <= 1.0
 
 
 def test_full_size_8192_one_fault_per_tile(h):
     """The full-size operands, automatic configuration, one +1e7 fault in
     every tile at a seeded k-step, row and column, checked on the unscaled
-    codes (scales 1): every fault is corrected, and on three sampled tiles the
-    oracle replay classifies them must-detect, its event log equals the GPU's
-    and C matches it.  The bound at full K is about 4e5 here (heavy-tailed
-    rows: |a_i| ~ 900), so 1e7 is must-detect at every k-step."""
+    codes (scales 1): the oracle replays every tile with the GPU's applied
+    faults, classes every fault must-detect, its event log equals the GPU's
+    and C equals the replay element by element (corrected elements within
+    their check's beta_row).  The bound at full K is about 4e5 here
+    (heavy-tailed rows: |a_i| ~ 900), so 1e7 is must-detect at every k-step."""
     m = n = k = 8192
     Ac, _, Bc, _ = _full_operands(h[1][4])
     cfg = F.ftgemm_select_config(h[1][0], m, n, k).as_tuple()
@@ -234,15 +245,10 @@ def test_full_size_8192_one_fault_per_tile(h):
     assert st == F.OK and rep.report.config.as_tuple()[:4] == cfg[:4]
     assert len(log) == len(sites) == ntiles
     assert rep.report.corrected == ntiles and rep.report.uncorrectable == 0
-    tiles = [(0, 0), (m // cfg[0] - 1, n // cfg[1] - 1), (5, 17)]
-    in_sample = lambda e: (int(e["tile_m"]), int(e["tile_n"])) in tiles
-    part = log[np.array([in_sample(l) for l in log], dtype=bool)]
     A, B = _decoded(h, Ac, Bc)
-    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, part, tiles=tiles)
-    assert bad == 0 and len(part) == len(tiles)
-    assert np.all(cls["cls"] == O.CLS_MUST)
-    ev = rep.events[np.array([in_sample(e) for e in rep.events], dtype=bool)]
-    assert event_keys(ev) == event_keys(res.events)
-    for (tm, tn) in tiles:
-        sl = (slice(tm * cfg[0], (tm + 1) * cfg[0]), slice(tn * cfg[1], (tn + 1) * cfg[1]))
-        assert rel_fro(C[sl], res.C[sl]) <= TOL_ACC[h[1][4]], (tm, tn)
+    res, cls, _, bad = replay_against_gpu(A, B, cfg, rep, log)
+    assert bad == 0 and np.all(cls["cls"] == O.CLS_MUST)
+    assert event_keys(rep.events) == event_keys(res.events)
+    assert rel_fro(C, res.C) <= TOL_ACC[h[1][4]]
+    assert elementwise_ratio(C, res.C, A, B, cfg, events=rep.events, oracle_events=res.events, log=log,
+                             acc_u=ACC_U[h[1][4]]) <= 1.0
