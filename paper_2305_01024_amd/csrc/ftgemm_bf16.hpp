@@ -182,9 +182,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
         }
     };
 
-    // registers -> LDS (A transposed to k-contiguous rows), fused with the
-    // encodings e^T A and B e in FP32 (section 2.2, Eq. 1-2)
-    auto store_panels = [&](int buf, int slot) {
+    // registers -> LDS (A transposed to k-contiguous rows)
+    auto store_panels = [&](int buf) {
         // A: column e of the thread's block holds rows 8ac..8ac+7 as bf16
         // pairs; row r gathers element r of columns 0..3 into 8 bytes.
 #pragma unroll
@@ -202,6 +201,12 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             const int kc = f % BKC, jj = f / BKC;
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][8 * kc]) = rb[r];
         }
+    };
+    // the encodings e^T A and B e of the staged panels in FP32 (section 2.2,
+    // Eq. 1-2), from the staging registers.  The FT kernels run them one
+    // sub-step after the LDS stores, after the step's last MFMAs (5% faster
+    // online at 8192^3 than right after the stores).
+    auto encode_panels = [&](int slot) {
         if constexpr (FT > 0) {
             // one v_dot2 per packed pair (an FP32 add of an exact product)
             const unsigned sel_ones = opaque_sgpr(kBfOnes), sel_lo = opaque_sgpr(kBfLo), sel_hi = opaque_sgpr(kBfHi);
@@ -329,7 +334,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             mfma_sub(cur, s);
             if constexpr (FT > 0) ft_sub(cur, t % 3, s);
             if constexpr (NEXT) {
-                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3);
+                if (s == BK / 16 - 2) store_panels(cur ^ 1);
+                if (s == BK / 16 - 1) encode_panels((t + 1) % 3);
             }
         }
     };
@@ -346,7 +352,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
     };
 
     load_panels(0);
-    store_panels(0, 0);
+    store_panels(0);
+    encode_panels(0);
     __syncthreads();
     for (int t = 0; t + 1 < nk; ++t) {
         step(t, std::true_type{});

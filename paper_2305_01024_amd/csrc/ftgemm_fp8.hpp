@@ -185,9 +185,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         }
     };
 
-    // registers -> LDS (A transposed to k-contiguous rows), fused with the
-    // encodings e^T A and B e in FP32 (section 2.2, Eq. 1-2)
-    auto store_panels = [&](int buf, int slot, auto set) {
+    // registers -> LDS (A transposed to k-contiguous rows)
+    auto store_panels = [&](int buf, auto set) {
         const u32x2* ra = ras[decltype(set)::value];
         const u32x4* rb = rbs[decltype(set)::value];
         // column e of the block holds rows 8 ac .. 8 ac + 7 as bytes; row r
@@ -205,6 +204,13 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             const int kc = f % BKC, jj = f / BKC;
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][16 * kc]) = rb[r];
         }
+    };
+    // the encodings e^T A and B e of the staged panels in FP32 (section 2.2,
+    // Eq. 1-2), from the staging registers, one sub-step after the LDS
+    // stores (after the step's last MFMAs)
+    auto encode_panels = [&](int slot, auto set) {
+        const u32x2* ra = ras[decltype(set)::value];
+        const u32x4* rb = rbs[decltype(set)::value];
         if constexpr (FT > 0) {
             // e^T A for the thread's 4 k over its 8 rows, then over the 4
             // lanes of the same k-quad in the wave (bits 4, 5): the
@@ -332,7 +338,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             if (s < MI) mfma_sub(cur, s);
             if constexpr (FT > 0) ft_sub(cur, t % 3, s);
             if constexpr (NEXT) {
-                if (s == BK / 16 - 2) store_panels(cur ^ 1, (t + 1) % 3, held);
+                if (s == BK / 16 - 2) store_panels(cur ^ 1, held);
+                if (s == BK / 16 - 1) encode_panels((t + 1) % 3, held);
             }
         }
     };
@@ -349,7 +356,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     };
 
     load_panels(0, S0{});
-    store_panels(0, 0, S0{});
+    store_panels(0, S0{});
+    encode_panels(0, S0{});
     if constexpr (NS == 2) {
         if (nk > 1) load_panels(1, S1{});
     }
