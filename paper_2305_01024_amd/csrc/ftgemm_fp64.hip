@@ -94,6 +94,28 @@ __device__ __forceinline__ double swap_sum64(double x) {
     const double d1 = __longlong_as_double((long long)(((unsigned long long)b1 << 32) | a1));
     return d0 + d1;
 }
+// Butterfly level on lane bit 4 or 5 of two doubles: lanes whose bit is
+// clear keep `lo`, lanes whose bit is set keep `hi`, and every lane gets its
+// kept value plus its partner's (lane l ^ (1 << BIT)); one swap per 32-bit
+// half, as in swap_sum64.
+template <int BIT>
+__device__ __forceinline__ double swap_add64(double lo, double hi) {
+    const unsigned long long ul = (unsigned long long)__double_as_longlong(lo);
+    const unsigned long long uh = (unsigned long long)__double_as_longlong(hi);
+    unsigned a0, a1, b0, b1;
+    if constexpr (BIT == 4) {
+        const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)ul, (unsigned)uh, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)(ul >> 32), (unsigned)(uh >> 32), false, false);
+        a0 = rl[0]; a1 = rl[1]; b0 = rh[0]; b1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)ul, (unsigned)uh, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)(ul >> 32), (unsigned)(uh >> 32), false, false);
+        a0 = rl[0]; a1 = rl[1]; b0 = rh[0]; b1 = rh[1];
+    }
+    const double d0 = __longlong_as_double((long long)(((unsigned long long)b0 << 32) | a0));
+    const double d1 = __longlong_as_double((long long)(((unsigned long long)b1 << 32) | a1));
+    return d0 + d1;
+}
 // Sum over the 16 lanes of a row (lane bits 0..3), in every lane of it.
 // Ascending levels: after bits 0 .. b-1 are summed, the partners
 // quad_perm [3,2,1,0] (l ^ 3) and row_half_mirror (l ^ 7 within 8) hold the
@@ -195,12 +217,16 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             s.Bs[buf][kk + 1][j] = rb[r][1];
         }
         if constexpr (FT > 0) {
-            // e^T A: wave `wave` holds all 128 rows of column 4 r + wave
+            // e^T A: wave `wave` holds all 128 rows of columns 4 r + wave,
+            // r = 0..3; a reduce-scatter over the wave (bit 5 halves the four
+            // column sums, bit 4 halves them again, bits 0..3 finish) leaves
+            // column r = 2 bit5 + bit4 in each row of 16 lanes
+            double x[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double w = wave_sum64(ra[r][0] + ra[r][1]);
-                if (lane == 0) s.wsum[buf][4 * r + wave] = w;
-            }
+            for (int r = 0; r < 4; ++r) x[r] = ra[r][0] + ra[r][1];
+            const double y0 = swap_add64<5>(x[0], x[2]), y1 = swap_add64<5>(x[1], x[3]);
+            const double w = row_sum64(swap_add64<4>(y0, y1));
+            if ((lane & 15) == 0) s.wsum[buf][4 * ((lane >> 4) & 3) + wave] = w;
             // B e: the thread's 4 columns of its k pair, then the 8 lanes of
             // the wave with the same k pair (lane bits 3..5), then the waves
             double v0 = 0.0, v1 = 0.0;
