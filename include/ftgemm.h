@@ -301,8 +301,9 @@ int ftgemm_run_z64(ftgemm_t handle, int64_t m, int64_t n, int64_t k, const doubl
                    ftgemm_report_t* report);
 
 /* One problem of a batched call: C = alpha * (scale_a A) (scale_b B) +
- * beta * C, column-major as in ftgemm_run, with its own dtype (FTGEMM_F32 or
- * FTGEMM_BF16), sizes, scales and device pointers (96 bytes). */
+ * beta * C, column-major as in ftgemm_run, with its own dtype (FTGEMM_F32,
+ * FTGEMM_BF16 or FTGEMM_F8E4M3), sizes, scales and device pointers
+ * (96 bytes). */
 typedef struct {
     int32_t dtype;
     int32_t reserved_;        /* must be 0 */
@@ -316,7 +317,8 @@ typedef struct {
 /* Many independent FT-GEMMs in one persistent launch (section 4.2.3 ABFT per
  * output tile, applied to every tile of every problem).  Each problem gets
  * its tile shape from the batched tile variants (FP32 128x128 or 64x64, BF16
- * 128x128) by the cost model of ftgemm_tune_batched, and a check every 256 k.
+ * 128x128, FP8 128x128) by the cost model of ftgemm_tune_batched, and a check
+ * every 256 k.
  * The workgroups of a persistent grid walk a cost-ordered list of (problem,
  * tile) items.  Events carry the problem index.  The per-problem plan is
  * built on the host and kept in the handle: a call with the same problem
@@ -324,7 +326,7 @@ typedef struct {
  * allocates nothing, so with report == NULL it can be captured into a HIP
  * graph (a different list under stream capture returns FTGEMM_INVALID with
  * bad_arg 3).  An invalid problem returns FTGEMM_INVALID with bad_arg 3 and
- * its index in report->bad_problem.  FP8 problems are not supported here. */
+ * its index in report->bad_problem. */
 int ftgemm_batched(ftgemm_t handle, int count, const ftgemm_problem_t* probs, int ft_level, float tol,
                    hipStream_t stream, ftgemm_report_t* report);
 
@@ -361,8 +363,8 @@ int ftgemm_add_tuned(ftgemm_t handle, const ftgemm_tuned_t* entry);
  * multiply-adds per second, measured by one timed batched launch per variant
  * on 64 problems of 512 x 512 x 512 with operands allocated for the purpose.
  * Without it the model uses built-in relative rates.  rates (may be NULL)
- * receives the measured value per variant (3 entries: FP32 128x128,
- * FP32 64x64, BF16 128x128).  Synchronises `stream`. */
+ * receives the measured value per variant (4 entries: FP32 128x128,
+ * FP32 64x64, BF16 128x128, FP8 128x128).  Synchronises `stream`. */
 int ftgemm_tune_batched(ftgemm_t handle, hipStream_t stream, double* rates);
 
 /* Fault injection hook (section 5.3: errors placed in the accumulator

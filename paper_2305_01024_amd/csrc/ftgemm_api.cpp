@@ -48,8 +48,9 @@ struct ftgemm_ctx {
     int bitems_cap = 0;
     int n_items = 0;
     int grid = 0;
+    bool plan_fp8 = false;   // the plan has FP8 problems: launch the kernel that holds the FP8 tile
     // cost model of the batched tile variants: multiply-adds per second
-    double batch_rate[kBatchVariants] = {4.0e13, 2.0e13, 1.6e14};
+    double batch_rate[kBatchVariants] = {4.0e13, 2.0e13, 1.6e14, 1.7e14};
 };
 
 namespace {
@@ -188,7 +189,7 @@ bool dims_ok(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t 
 int first_bad_problem(int count, const ftgemm_problem_t* probs) {
     for (int p = 0; p < count; ++p) {
         const ftgemm_problem_t& q = probs[p];
-        if (q.dtype != FTGEMM_F32 && q.dtype != FTGEMM_BF16) return p;
+        if (q.dtype != FTGEMM_F32 && q.dtype != FTGEMM_BF16 && q.dtype != FTGEMM_F8E4M3) return p;
         if (q.reserved_ != 0 || !dims_ok(q.m, q.n, q.k, q.lda, q.ldb, q.ldc)) return p;
         if (q.m > 0 && q.n > 0 && !q.C) return p;
         if (q.m > 0 && q.n > 0 && q.k > 0 && q.alpha != 0.f && (!q.A || !q.B)) return p;
@@ -284,7 +285,9 @@ int build_plan(ftgemm_ctx* h, int count, const ftgemm_problem_t* probs) {
     if (!items.empty())
         FT_HIP(hipMemcpy(h->d_bitems, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
     h->n_items = (int)items.size();
-    h->grid = std::max(1, std::min(h->n_items, batch_resident_blocks(h->device)));
+    h->plan_fp8 = false;
+    for (const BatchProblem& d : bp) h->plan_fp8 = h->plan_fp8 || (d.variant >= 0 && batch_variant_dtype(d.variant) == FTGEMM_F8E4M3);
+    h->grid = std::max(1, std::min(h->n_items, batch_resident_blocks(h->device, h->plan_fp8)));
     h->plan_probs.assign(probs, probs + count);
     h->plan_cfg = cfgs;
     h->plan_valid = true;
@@ -951,7 +954,7 @@ int ftgemm_batched(ftgemm_t h, int count, const ftgemm_problem_t* probs, int ft_
     b.n_faults = inject ? h->n_faults : 0;
     b.fault_log_cap = h->flog_cap;
     b.fault_log = h->d_flog;
-    FT_HIP(launch_batched(b, inject, h->grid, stream));
+    FT_HIP(launch_batched(b, inject, h->grid, h->plan_fp8, stream));
     if (!report) return FTGEMM_OK;
     return fill_report(h, stream, report);
 }
@@ -1093,7 +1096,7 @@ int ftgemm_tune_batched(ftgemm_t h, hipStream_t stream, double* rates) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int st = FTGEMM_OK;
     const size_t ab = 4 * (size_t)kDim * kDim, cb = 4 * (size_t)kDim * kDim;
-    double measured[kBatchVariants] = {0, 0, 0};
+    double measured[kBatchVariants] = {};
     const bool had_plan = h->plan_valid;
     if (hipMalloc(&A, ab * kProbs) != hipSuccess || hipMalloc(&B, ab * kProbs) != hipSuccess ||
         hipMalloc(&C, cb * kProbs) != hipSuccess) {
@@ -1103,7 +1106,8 @@ int ftgemm_tune_batched(ftgemm_t h, hipStream_t stream, double* rates) {
         st = FTGEMM_HIP_ERROR;
     } else {
         // each variant alone: force it by giving the model a single admissible rate
-        const double saved[kBatchVariants] = {h->batch_rate[0], h->batch_rate[1], h->batch_rate[2]};
+        double saved[kBatchVariants];
+        for (int u = 0; u < kBatchVariants; ++u) saved[u] = h->batch_rate[u];
         for (int v = 0; v < kBatchVariants && st == FTGEMM_OK; ++v) {
             for (int u = 0; u < kBatchVariants; ++u) h->batch_rate[u] = (u == v) ? 1.0 : 1e-30;
             std::vector<ftgemm_problem_t> probs(kProbs);

@@ -6,24 +6,31 @@
 // item runs the same tile computation as the single-problem kernels (the
 // threadblock-level online ABFT of section 4.2.3, with its own encode,
 // checksum update, checks and correction), on the item's problem: one tile
-// shape per problem, picked on the host.  The LDS of the three tile variants
-// is one union.
+// shape per problem, picked on the host.  The LDS of the tile variants is
+// one union.  A plan with FP8 problems launches the instantiation that also
+// holds the FP8 tile (F8); the others leave it out and keep the register
+// allocation of the FP32 and BF16 paths as it is without it.
 #include "ftgemm_bf16.hpp"
 #include "ftgemm_fp32.hpp"
+#include "ftgemm_fp8.hpp"
 
 namespace ftgemm_impl {
 namespace {
 
 constexpr int kBatchThreads = 256;
 
+struct NoLds {};
+template <bool F8>
 union BatchSmem {
     f32::Smem<128, 128, 32, 2, 2> f32_128;
     f32::Smem<64, 64, 64, 2, 2> f32_64;
     bf16::SmemBF16<128, 128, 64, 2, 2> bf16_128;
+    std::conditional_t<F8, fp8::SmemFP8<128, 128, 64, 2, 2>, NoLds> fp8_128;
 };
 
-constexpr Variant kBatchVariantTable[kBatchVariants] = {{128, 128, 32, 128, 128}, {64, 64, 64, 64, 64}, {128, 128, 64, 128, 128}};
-constexpr int kBatchVariantDtype[kBatchVariants] = {FTGEMM_F32, FTGEMM_F32, FTGEMM_BF16};
+constexpr Variant kBatchVariantTable[kBatchVariants] = {
+    {128, 128, 32, 128, 128}, {64, 64, 64, 64, 64}, {128, 128, 64, 128, 128}, {128, 128, 64, 128, 128}};
+constexpr int kBatchVariantDtype[kBatchVariants] = {FTGEMM_F32, FTGEMM_F32, FTGEMM_BF16, FTGEMM_F8E4M3};
 
 // C = beta * C on one 128 x 128 tile (problems with k == 0 or alpha == 0)
 __device__ void scale_tile(const BatchProblem& p, int tm, int tn) {
@@ -36,9 +43,9 @@ __device__ void scale_tile(const BatchProblem& p, int tm, int tn) {
     }
 }
 
-template <int FT, bool INJ>
+template <int FT, bool INJ, bool F8>
 __global__ __launch_bounds__(kBatchThreads, 2) void ftgemm_batched_kernel(BatchArgs b) {
-    __shared__ BatchSmem sm;
+    __shared__ BatchSmem<F8> sm;
     for (int it = blockIdx.x; it < b.n_items; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchProblem& p = b.probs[item.problem];
@@ -77,15 +84,24 @@ __global__ __launch_bounds__(kBatchThreads, 2) void ftgemm_batched_kernel(BatchA
         switch (p.variant) {
             case 0: f32::tile<128, 128, 32, 2, 2, FT, INJ>(a, tm, tn, sm.f32_128); break;
             case 1: f32::tile<64, 64, 64, 2, 2, FT, INJ>(a, tm, tn, sm.f32_64); break;
-            default: bf16::tile<128, 128, 64, 2, 2, FT, INJ>(a, tm, tn, sm.bf16_128); break;
+            default:
+                if constexpr (F8) {
+                    if (p.variant == 3) {
+                        fp8::tile<128, 128, 64, 2, 2, FT, INJ>(a, tm, tn, sm.fp8_128);
+                        break;
+                    }
+                }
+                bf16::tile<128, 128, 64, 2, 2, FT, INJ>(a, tm, tn, sm.bf16_128);
+                break;
         }
         __syncthreads();   // the next item reuses the LDS
     }
 }
 
 template <int FT, bool INJ>
-hipError_t launch_level(const BatchArgs& b, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((ftgemm_batched_kernel<FT, INJ>), dim3((unsigned)grid), dim3(kBatchThreads), 0, s, b);
+hipError_t launch_level(const BatchArgs& b, int grid, bool fp8, hipStream_t s) {
+    if (fp8) hipLaunchKernelGGL((ftgemm_batched_kernel<FT, INJ, true>), dim3((unsigned)grid), dim3(kBatchThreads), 0, s, b);
+    else hipLaunchKernelGGL((ftgemm_batched_kernel<FT, INJ, false>), dim3((unsigned)grid), dim3(kBatchThreads), 0, s, b);
     return hipGetLastError();
 }
 
@@ -94,25 +110,27 @@ hipError_t launch_level(const BatchArgs& b, int grid, hipStream_t s) {
 Variant batch_variant(int v) { return kBatchVariantTable[v]; }
 int batch_variant_dtype(int v) { return kBatchVariantDtype[v]; }
 
-int batch_resident_blocks(int device) {
+int batch_resident_blocks(int device, bool fp8) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ftgemm_batched_kernel<2, false>, kBatchThreads, 0) !=
-        hipSuccess)
-        per_cu = 1;
+    const hipError_t e = fp8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ftgemm_batched_kernel<2, false, true>,
+                                                                             kBatchThreads, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ftgemm_batched_kernel<2, false, false>,
+                                                                             kBatchThreads, 0);
+    if (e != hipSuccess) per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
     return std::max(1, per_cu) * std::max(1, cus);
 }
 
-hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, hipStream_t s) {
+hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, bool fp8, hipStream_t s) {
     if (b.n_items <= 0) return hipSuccess;
     if (inject) {
-        if (b.ft_level == 0) return launch_level<0, true>(b, grid, s);
-        if (b.ft_level == 1) return launch_level<1, true>(b, grid, s);
-        return launch_level<2, true>(b, grid, s);
+        if (b.ft_level == 0) return launch_level<0, true>(b, grid, fp8, s);
+        if (b.ft_level == 1) return launch_level<1, true>(b, grid, fp8, s);
+        return launch_level<2, true>(b, grid, fp8, s);
     }
-    if (b.ft_level == 0) return launch_level<0, false>(b, grid, s);
-    if (b.ft_level == 1) return launch_level<1, false>(b, grid, s);
-    return launch_level<2, false>(b, grid, s);
+    if (b.ft_level == 0) return launch_level<0, false>(b, grid, fp8, s);
+    if (b.ft_level == 1) return launch_level<1, false>(b, grid, fp8, s);
+    return launch_level<2, false>(b, grid, fp8, s);
 }
 
 }  // namespace ftgemm_impl

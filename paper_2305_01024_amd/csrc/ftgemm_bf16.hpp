@@ -203,9 +203,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
         }
     };
     // the encodings e^T A and B e of the staged panels in FP32 (section 2.2,
-    // Eq. 1-2), from the staging registers.  The FT kernels run them one
-    // sub-step after the LDS stores, after the step's last MFMAs (5% faster
-    // online at 8192^3 than right after the stores).
+    // Eq. 1-2), from the staging registers.  The 256 x 256 FT kernels run
+    // them one sub-step after the LDS stores, after the step's last MFMAs (5%
+    // faster online at 8192^3 than right after the stores); the 128 x 128
+    // tile, which the batched kernel also holds, right after the stores (the
+    // later placement doubles the batched kernel's spills).
     auto encode_panels = [&](int slot) {
         if constexpr (FT > 0) {
             // one v_dot2 per packed pair (an FP32 add of an exact product)
@@ -335,7 +337,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             if constexpr (FT > 0) ft_sub(cur, t % 3, s);
             if constexpr (NEXT) {
                 if (s == BK / 16 - 2) store_panels(cur ^ 1);
-                if (s == BK / 16 - 1) encode_panels((t + 1) % 3);
+                if (s == (BM == 256 ? BK / 16 - 1 : BK / 16 - 2)) encode_panels((t + 1) % 3);
             }
         }
     };

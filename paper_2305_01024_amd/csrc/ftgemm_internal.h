@@ -169,13 +169,15 @@ struct BatchArgs {
 };
 
 // Tile variants of the batched kernel (one 256-thread workgroup per tile):
-// 0 = FP32 128 x 128 x 32, 1 = FP32 64 x 64 x 64, 2 = BF16 128 x 128 x 64.
-constexpr int kBatchVariants = 3;
+// 0 = FP32 128 x 128 x 32, 1 = FP32 64 x 64 x 64, 2 = BF16 128 x 128 x 64,
+// 3 = FP8 128 x 128 x 64 (only in the instantiation launched for plans with
+// FP8 problems).
+constexpr int kBatchVariants = 4;
 Variant batch_variant(int v);
 int batch_variant_dtype(int v);
 // Workgroups of the batched kernel that are resident on the device at once.
-int batch_resident_blocks(int device);
-hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, hipStream_t stream);
+int batch_resident_blocks(int device, bool fp8);
+hipError_t launch_batched(const BatchArgs& b, bool inject, int grid, bool fp8, hipStream_t stream);
 
 // ---- non-fused ABFT (the same checks around the plain kernel, one launch per step) ----
 constexpr int kNonFusedTile = 256;   // check tile, rows and columns

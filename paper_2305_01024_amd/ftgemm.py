@@ -400,6 +400,6 @@ def load_tuned(handle: int, path: str) -> int:
 
 def ftgemm_tune_batched(handle: int, stream: int = 0) -> np.ndarray:
     """Measure the batched tile variants' rates (multiply-adds per second)."""
-    rates = (ctypes.c_double * 3)()
+    rates = (ctypes.c_double * 4)()
     _check(lib().ftgemm_tune_batched(handle, stream, rates), "ftgemm_tune_batched")
     return np.array(list(rates))

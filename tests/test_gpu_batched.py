@@ -49,6 +49,13 @@ class Batch:
                 A64, B64 = O.decode_bf16(Ac), O.decode_bf16(Bc)
                 dA = torch.from_numpy(np.ascontiguousarray(Ac.T).view(np.int16)).cuda() if Ac.size else torch.zeros(1, device="cuda")
                 dB = torch.from_numpy(np.ascontiguousarray(Bc.T).view(np.int16)).cuda() if Bc.size else torch.zeros(1, device="cuda")
+            elif dt == "fp8":
+                # codes of the unscaled operands (U[-1, 1] fits E4M3 as it is; scales 1)
+                Ac = np.asfortranarray(W.to_e4m3_codes(A.astype(np.float64)))
+                Bc = np.asfortranarray(W.to_e4m3_codes(B.astype(np.float64)))
+                A64, B64 = O.decode_e4m3(Ac), O.decode_e4m3(Bc)
+                dA = torch.from_numpy(np.ascontiguousarray(Ac.T)).cuda() if Ac.size else torch.zeros(1, device="cuda")
+                dB = torch.from_numpy(np.ascontiguousarray(Bc.T)).cuda() if Bc.size else torch.zeros(1, device="cuda")
             else:
                 A64, B64 = A.astype(np.float64), B.astype(np.float64)
                 dA = torch.from_numpy(np.ascontiguousarray(A.T)).cuda() if A.size else torch.zeros(1, device="cuda")
@@ -57,7 +64,7 @@ class Batch:
             self.host.append((np.asfortranarray(A64), np.asfortranarray(B64), C0))
             self.dev.append((dA, dB, dC))
             q = self.probs[p]
-            q["dtype"] = F.BF16 if dt == "bf16" else F.F32
+            q["dtype"] = {"bf16": F.BF16, "fp8": F.F8E4M3}.get(dt, F.F32)
             q["m"], q["n"], q["k"] = m, n, k
             q["lda"], q["ldb"], q["ldc"] = max(1, m), max(1, k), max(1, m)
             q["alpha"], q["beta"], q["scale_a"], q["scale_b"] = alpha, beta, 1.0, 1.0
@@ -96,6 +103,24 @@ def test_batched_matches_oracle_per_problem(h):
         assert rel_fro(bt.result(p), bt.reference(p)) <= TOL, (p, shapes[p])
     used = {F.ftgemm_batched_config(h, p).as_tuple()[:3] for p in range(len(shapes))}
     assert (128, 128, 32) in used and (128, 128, 64) in used
+
+
+def test_batched_fp8_problems_match_oracle(h):
+    """FP8 E4M3 problems in a batch with FP32 and BF16 ones: each FP8
+    problem runs the FP8 128 x 128 variant and matches the oracle on its
+    decoded codes (relative Frobenius 1e-4: the FP8 instruction sums its
+    products below binary32 precision), the others as before."""
+    import torch
+    shapes = [(300, 200, 257, "fp8"), (64, 64, 64, "fp8"), (1, 130, 70, "fp8"), (256, 256, 512, "f32"),
+              (200, 300, 100, "bf16"), (513, 129, 65, "fp8")]
+    bt = Batch(shapes, 503, beta=0.5)
+    rep = F.ReportBuffer(64)
+    st = F.ftgemm_batched(h, bt.probs, F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream, rep)
+    assert st == F.OK and rep.report.n_events == 0 and rep.report.checks > 0
+    for p, (m, n, k, dt) in enumerate(shapes):
+        assert rel_fro(bt.result(p), bt.reference(p)) <= (1e-4 if dt == "fp8" else TOL), (p, shapes[p])
+        if dt == "fp8":
+            assert F.ftgemm_batched_config(h, p).as_tuple()[:3] == (128, 128, 64)
 
 
 def test_batched_alpha_zero_and_beta_zero_quick_returns(h):
@@ -233,7 +258,7 @@ def test_tune_picks_a_config_that_runs_used_and_persisted(h, tmp_path):
 def test_tune_batched_measures_every_variant(h):
     import torch
     rates = F.ftgemm_tune_batched(h, torch.cuda.current_stream().cuda_stream)
-    assert rates.shape == (3,) and np.all(rates > 1e11)
+    assert rates.shape == (4,) and np.all(rates > 1e11)
 
 
 def test_full_size_1024_problems_sampled(h):
