@@ -69,11 +69,13 @@ struct F64Lds {
 // lane l ^ (1 << BIT) for BIT = 4 or 5 (v_permlane16/32_swap with both
 // operands the value itself returns the own value in one result and the
 // partner's in the other, so their sum is the pair's sum).
+// (Only controls whose source lane is always valid are used, so the moves
+// need no old value.)
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double x) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 template <int BIT>
@@ -132,9 +134,30 @@ __device__ __forceinline__ double wave_sum64(double x) {
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double flip64(double v, int bit) {
     return __longlong_as_double(__double_as_longlong(v) ^ (long long)(1ull << (bit & 63)));
+}
+
+// Per-lane indices of the thread.  lanes() passes threadIdx.x through an
+// empty asm, so what the staging and the check derive from them (offsets,
+// addresses) is computed where it is used rather than hoisted out of the
+// k-loop, where it would hold a register, or a spill slot reloaded at every
+// step, for the whole loop.
+struct Lanes {
+    int tid, lane, li, lg, own;
+};
+__device__ __forceinline__ Lanes lanes() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    Lanes L;
+    L.tid = t;
+    L.lane = t & 63;
+    L.li = t & 15;
+    L.lg = (t >> 4) & 3;
+    L.own = t & (BM - 1);   // owned tile row (threads 0..127) or column (128..255)
+    return L;
 }
 
 // One 128 x 128 tile (tm, tn).  FT: 0 plain, 1 detect-only, 2 online.
@@ -146,8 +169,8 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
     const int i0 = tm * BM, j0 = tn * BN;
     const int mI = min(BM, a.M - i0), nJ = min(BN, a.N - j0);
     const int nk = (a.K + BK - 1) / BK;
-    const bool row_owner = tid < BM;
-    const int own = row_owner ? tid : tid - BM;   // owned tile row or column
+    const bool row_owner = wave < BM / 64;        // threads 0..127 own rows (uniform per wave)
+    const int own = tid & (BM - 1);               // owned tile row or column
 
     f64x4 accm[4][4];   // matrix-core blocks [bj][bi]
 #pragma unroll
@@ -183,36 +206,83 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
     // ---- staging: each thread holds 4 pairs of A (rows 2p, 2p+1 of column k = 4 r + wave)
     // and 4 pairs of B (k = 2 (tid % 8), +1 of column j = tid / 8 + 32 r) ----
     double ra[4][2], rb[4][2];
+    // Interior panels (the whole k-step inside K, the whole tile inside M or
+    // N, 16-byte aligned pairs): one 16-byte buffer load per pair, with the
+    // per-lane byte offset fixed for the whole k-loop, the per-step origin in
+    // the scalar resource base and the per-slot offset in a scalar register,
+    // so the loop carries no vector address arithmetic or bounds selects.
+    const bool vecA = ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) && ((a.lda & 1) == 0) &&
+                      (int64_t)BK * a.lda * 8 < (int64_t(1) << 31);
+    const bool vecB = ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0) && ((a.ldb & 1) == 0) &&
+                      (int64_t)BN * a.ldb * 8 < (int64_t(1) << 31);
+    constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
     auto load = [&](int t) {
+        const Lanes L = lanes();
+        const int voffA = 16 * L.lane;                                      // rows 2 lane, 2 lane + 1
+        const int voffB = ((L.tid / 8) * (int)a.ldb + 2 * (L.tid % 8)) * 8;  // k pair 2 (tid % 8) of column tid / 8
         const int k0 = t * BK;
+        const bool fullk = k0 + BK <= a.K;
+        // the edge paths take their k origin through an empty asm so that the
+        // loop optimiser cannot turn their per-element pointers into
+        // induction variables advanced on every step of the interior path
+        int k0e = k0;
+        asm volatile("" : "+s"(k0e));
+        if (vecA && fullk && mI == BM) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.A + i0 + (size_t)k0 * a.lda),
+                                                              (short)0, 0x7fffffff, kRsrcWord3);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = 4 * r + wave, i = 2 * lane;
-            const int gk = k0 + k;
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const bool in = gk < a.K && i + e < mI;
-                const double* p = in ? a.A + (size_t)gk * a.lda + (i0 + i + e) : a.A;
-                const double x = *p;
-                ra[r][e] = in ? x : 0.0;
+            for (int r = 0; r < 4; ++r) {
+                const f64x2 v = __builtin_bit_cast(
+                    f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, voffA, (4 * r + wave) * (int)a.lda * 8, 0));
+                ra[r][0] = v[0];
+                ra[r][1] = v[1];
             }
-            const int j = tid / 8 + 32 * r, kk = 2 * (tid % 8);
+        } else {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const bool in = k0 + kk + e < a.K && j < nJ;
-                const double* p = in ? a.B + (size_t)(j0 + j) * a.ldb + (k0 + kk + e) : a.B;
-                const double x = *p;
-                rb[r][e] = in ? x : 0.0;
+            for (int r = 0; r < 4; ++r) {
+                const int gk = k0e + 4 * r + wave, i = 2 * L.lane;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const bool in = gk < a.K && i + e < mI;
+                    const double* p = in ? a.A + (size_t)gk * a.lda + (i0 + i + e) : a.A;
+                    const double x = *p;
+                    ra[r][e] = in ? x : 0.0;
+                }
+            }
+        }
+        if (vecB && fullk && nJ == BN) {
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.B + (size_t)j0 * a.ldb + k0),
+                                                              (short)0, 0x7fffffff, kRsrcWord3);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const f64x2 v = __builtin_bit_cast(
+                    f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB, 32 * r * (int)a.ldb * 8, 0));
+                rb[r][0] = v[0];
+                rb[r][1] = v[1];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = L.tid / 8 + 32 * r, kk = 2 * (L.tid % 8);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const bool in = k0e + kk + e < a.K && j < nJ;
+                    const double* p = in ? a.B + (size_t)(j0 + j) * a.ldb + (k0e + kk + e) : a.B;
+                    const double x = *p;
+                    rb[r][e] = in ? x : 0.0;
+                }
             }
         }
     };
     auto store = [&](int buf, int vslot) {
+        const Lanes L = lanes();
+        const int lane = L.lane;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int k = 4 * r + wave, i = 2 * lane;
             s.As[buf][k][i] = ra[r][0];
             s.As[buf][k][i + 1] = ra[r][1];
-            const int j = tid / 8 + 32 * r, kk = 2 * (tid % 8);
+            const int j = L.tid / 8 + 32 * r, kk = 2 * (L.tid % 8);
             s.Bs[buf][kk][j] = rb[r][0];
             s.Bs[buf][kk + 1][j] = rb[r][1];
         }
@@ -245,6 +315,8 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
 
     // ---- online check after k-step t (kp = k indices accumulated) ----
     auto check = [&](int t, int kp) {
+        const Lanes L = lanes();
+        const int tid = L.tid, lane = L.lane, li = L.li, lg = L.lg, own = L.own;
         // row sums: a lane's 16 values of a block row, then lane bits 4, 5,
         // then the two wave columns in LDS; column sums: the four blocks
         // of a lane's column, then lane bits 0..3, then the two wave rows
