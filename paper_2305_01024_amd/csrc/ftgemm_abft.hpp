@@ -375,6 +375,16 @@ __device__ __forceinline__ void log_nonfinite(const LaunchArgs& a, int tile_m, i
     }
 }
 
+// threadIdx.x through an empty asm: per-lane offsets and addresses a k-step
+// derives from it are then computed inside the step instead of being hoisted
+// out of the k-loop, where they would hold registers (or spill slots,
+// reloaded at every step) for the whole loop.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // The per-lane indices, passed through an empty asm at the start of a check:
 // the addresses the check derives from them are then computed inside it
 // rather than hoisted out of the k-loop, where they would hold registers (or
@@ -386,8 +396,8 @@ __device__ __forceinline__ Thread opaque_lanes(const Thread& th) {
 }
 
 template <class G, int FT, bool INJ>
-__device__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th_loop, int t, int kp,
-                      float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
+__device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchArgs& a, const Thread& th_loop, int t, int kp,
+                                      float& Rr, float& na2, float& Sc, float& nb2, int fnext, int& flogged) {
     constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN, WM = G::WM, WN = G::WN, NW = G::NW;
     const Thread th = opaque_lanes(th_loop);
     const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;

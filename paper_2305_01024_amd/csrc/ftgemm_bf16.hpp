@@ -126,7 +126,17 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
     }
     constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
 
+    // The per-lane staging indices above are kept for the whole k-loop by the
+    // 256 x 256 kernels.  The 128 x 128 tile, which the batched kernel
+    // compiles beside its other tile variants, re-derives them from
+    // opaque_tid() inside every step: kept, they were spilled there and
+    // reloaded at every step (re-deriving them in the 256 x 256 kernels cost
+    // the plain kernel 13% at 8192^3).
+    constexpr bool OPQ = BM == 128;
     auto load_panels = [&](int t) {
+        const int tid_s = OPQ ? opaque_tid() : tid;
+        const int akq_s = OPQ ? tid_s % AKQ : akq, ac_s = OPQ ? tid_s / AKQ : ac;
+        const int voffA_s = OPQ ? (4 * akq_s * (int)a.lda + 8 * ac_s) * 2 : voffA;
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
         // the edge paths take their k origin through an empty asm so that the
@@ -139,11 +149,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
                 const_cast<unsigned short*>(Abase + (size_t)k0 * a.lda), (short)0, 0x7fffffff, kRsrcWord3);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                ra[e] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffA, e * (int)a.lda * 2, 0));
+                ra[e] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffA_s, e * (int)a.lda * 2, 0));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gk = k0e + 4 * akq + e, gi = 8 * ac;
+                const int gk = k0e + 4 * akq_s + e, gi = 8 * ac_s;
                 const unsigned short* p = Abase + (size_t)gk * a.lda + gi;
                 unsigned v[8];
 #pragma unroll
@@ -160,12 +170,15 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned short*>(Bbase + k0), (short)0,
                                                               0x7fffffff, kRsrcWord3);
 #pragma unroll
-            for (int r = 0; r < NB; ++r)
-                rb[r] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB[r], 0, 0));
+            for (int r = 0; r < NB; ++r) {
+                const int f = tid_s + NT * r;
+                const int voffB_s = OPQ ? ((f / BKC) * (int)a.ldb + 8 * (f % BKC)) * 2 : voffB[r];
+                rb[r] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB_s, 0, 0));
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
+                const int f = tid_s + NT * r;
                 const int kc = f % BKC, jj = f / BKC;
                 const int gk = k0e + 8 * kc;
                 const unsigned short* p = Bbase + (size_t)jj * a.ldb + gk;
@@ -184,6 +197,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
 
     // registers -> LDS (A transposed to k-contiguous rows)
     auto store_panels = [&](int buf) {
+        const int tid_s = OPQ ? opaque_tid() : tid;
+        const int akq_s = OPQ ? tid_s % AKQ : akq, ac_s = OPQ ? tid_s / AKQ : ac;
         // A: column e of the thread's block holds rows 8ac..8ac+7 as bf16
         // pairs; row r gathers element r of columns 0..3 into 8 bytes.
 #pragma unroll
@@ -193,11 +208,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             u32x2 w;
             w[0] = __builtin_amdgcn_perm(ra[1][d], ra[0][d], sel);
             w[1] = __builtin_amdgcn_perm(ra[3][d], ra[2][d], sel);
-            *reinterpret_cast<u32x2*>(&op.As[buf][8 * ac + r][4 * akq]) = w;
+            *reinterpret_cast<u32x2*>(&op.As[buf][8 * ac_s + r][4 * akq_s]) = w;
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-            const int f = tid + NT * r;
+            const int f = tid_s + NT * r;
             const int kc = f % BKC, jj = f / BKC;
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][8 * kc]) = rb[r];
         }
@@ -210,6 +225,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
     // later placement doubles the batched kernel's spills).
     auto encode_panels = [&](int slot) {
         if constexpr (FT > 0) {
+            const int tid_s = OPQ ? opaque_tid() : tid;
+            const int lane_s = OPQ ? tid_s & 63 : lane, akq_s = OPQ ? tid_s % AKQ : akq;
             // one v_dot2 per packed pair (an FP32 add of an exact product)
             const unsigned sel_ones = opaque_sgpr(kBfOnes), sel_lo = opaque_sgpr(kBfLo), sel_hi = opaque_sgpr(kBfHi);
             // e^T A for the thread's 4 k over its 8 rows, then over the 32
@@ -223,8 +240,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
                 for (int d = 0; d < 4; ++d) x = dot2(ra[e][d], sel_ones, x);
                 ws[e] = x;
             }
-            ReduceScatter<4, 5, 4>::run(ws, lane);
-            atomicAdd(&op.wsum[slot][4 * akq + ((lane >> 4) & 3)], ws[0]);
+            ReduceScatter<4, 5, 4>::run(ws, lane_s);
+            atomicAdd(&op.wsum[slot][4 * akq_s + ((lane_s >> 4) & 3)], ws[0]);
             // B e for the thread's 8 k over its NB columns, then over the
             // lanes of the same k-chunk (bits 3..5): lane keeps
             // k = 8 kc + ((lane >> 3) & 7); waves add in LDS.
@@ -238,8 +255,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
                     vs[2 * d] = dot2(rb[r][d], sel_lo, vs[2 * d]);
                     vs[2 * d + 1] = dot2(rb[r][d], sel_hi, vs[2 * d + 1]);
                 }
-            ReduceScatter<8, 5, 3>::run(vs, lane);
-            atomicAdd(&op.vsum[slot][8 * (tid % BKC) + ((lane >> 3) & 7)], vs[0]);
+            ReduceScatter<8, 5, 3>::run(vs, lane_s);
+            atomicAdd(&op.vsum[slot][8 * (tid_s % BKC) + ((lane_s >> 3) & 7)], vs[0]);
         }
     };
 
@@ -327,7 +344,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
         const int cur = t & 1;
         if constexpr (NEXT) load_panels(t + 1);
         if constexpr (FT > 0 && NEXT) {   // slot for step t+2: its last reader finished before this step
-            const int x = tid < BK ? tid : BK - 1;
+            const int tz = OPQ ? opaque_tid() : tid, x = tz < BK ? tz : BK - 1;
             op.wsum[(t + 2) % 3][x] = 0.f;
             op.vsum[(t + 2) % 3][x] = 0.f;
         }

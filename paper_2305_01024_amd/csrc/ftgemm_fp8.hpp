@@ -126,9 +126,20 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     }
     constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format
 
+    // The plain 256 x 256 kernel keeps the per-lane staging indices above for
+    // the whole k-loop.  The FT kernels and the 128 x 128 tile (which the
+    // batched kernel compiles beside its other tile variants) re-derive them
+    // from opaque_tid() inside every step, which frees their registers for the
+    // encodings (online 8192^3 2.03 -> 1.86 ms); re-deriving them cost the
+    // plain kernel 5%.
+    constexpr bool OPQ = BM == 128 || FT > 0;
+
     auto load_panels = [&](int t, auto set) {
         u32x2* ra = ras[decltype(set)::value];
         u32x4* rb = rbs[decltype(set)::value];
+        const int tid_s = OPQ ? opaque_tid() : tid;
+        const int akq_s = OPQ ? tid_s % AKQ : akq, ac_s = OPQ ? tid_s / AKQ : ac;
+        const int voffA_s = OPQ ? 4 * akq_s * (int)a.lda + 8 * ac_s : voffA;
         const int k0 = t * BK;
         const bool fullk = k0 + BK <= a.K;
         // the edge paths take their k origin through an empty asm so that the
@@ -141,11 +152,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
                 const_cast<unsigned char*>(Abase + (size_t)k0 * a.lda), (short)0, 0x7fffffff, kRsrcWord3);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                ra[e] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voffA, e * (int)a.lda, 0));
+                ra[e] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voffA_s, e * (int)a.lda, 0));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gk = k0e + 4 * akq + e, gi = 8 * ac;
+                const int gk = k0e + 4 * akq_s + e, gi = 8 * ac_s;
                 const unsigned char* p = Abase + (size_t)gk * a.lda + gi;
                 unsigned v[8];
 #pragma unroll
@@ -162,12 +173,15 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(Bbase + k0), (short)0,
                                                               0x7fffffff, kRsrcWord3);
 #pragma unroll
-            for (int r = 0; r < NB; ++r)
-                rb[r] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB[r], 0, 0));
+            for (int r = 0; r < NB; ++r) {
+                const int f = tid_s + NT * r;
+                const int voffB_s = OPQ ? (f / BKC) * (int)a.ldb + 16 * (f % BKC) : voffB[r];
+                rb[r] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voffB_s, 0, 0));
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
-                const int f = tid + NT * r;
+                const int f = tid_s + NT * r;
                 const int kc = f % BKC, jj = f / BKC;
                 const int gk = k0e + 16 * kc;
                 const unsigned char* p = Bbase + (size_t)jj * a.ldb + gk;
@@ -189,6 +203,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
     auto store_panels = [&](int buf, auto set) {
         const u32x2* ra = ras[decltype(set)::value];
         const u32x4* rb = rbs[decltype(set)::value];
+        const int tid_s = OPQ ? opaque_tid() : tid;
+        const int akq_s = OPQ ? tid_s % AKQ : akq, ac_s = OPQ ? tid_s / AKQ : ac;
         // column e of the block holds rows 8 ac .. 8 ac + 7 as bytes; row r
         // gathers byte r of the 4 columns into one dword (k 4 akq .. +3).
 #pragma unroll
@@ -196,11 +212,11 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             const int d = r >> 2, sh = 8 * (r & 3);
             const unsigned w = ((ra[0][d] >> sh) & 0xffu) | (((ra[1][d] >> sh) & 0xffu) << 8) |
                                (((ra[2][d] >> sh) & 0xffu) << 16) | (((ra[3][d] >> sh) & 0xffu) << 24);
-            *reinterpret_cast<unsigned*>(&op.As[buf][8 * ac + r][4 * akq]) = w;
+            *reinterpret_cast<unsigned*>(&op.As[buf][8 * ac_s + r][4 * akq_s]) = w;
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-            const int f = tid + NT * r;
+            const int f = tid_s + NT * r;
             const int kc = f % BKC, jj = f / BKC;
             *reinterpret_cast<u32x4*>(&op.Bs[buf][jj][16 * kc]) = rb[r];
         }
@@ -214,6 +230,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
         const u32x2* ra = ras[decltype(set)::value];
         const u32x4* rb = rbs[decltype(set)::value];
         if constexpr (FT > 0) {
+            const int tid_s = OPQ ? opaque_tid() : tid;
+            const int lane_s = OPQ ? tid_s & 63 : lane, akq_s = OPQ ? tid_s % AKQ : akq;
             // e^T A for the thread's 4 k over its 8 rows, then over the 4
             // lanes of the same k-quad in the wave (bits 4, 5): the
             // reduce-scatter leaves k = 4 akq + ((lane >> 4) & 3); waves add
@@ -226,8 +244,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
                 decode4(ra[e][1], f1);
                 ws[e] = ((f0[0] + f0[1]) + (f0[2] + f0[3])) + ((f1[0] + f1[1]) + (f1[2] + f1[3]));
             }
-            ReduceScatter<4, 5, 4>::run(ws, lane);
-            atomicAdd(&op.wsum[slot][4 * akq + ((lane >> 4) & 3)], ws[0]);
+            ReduceScatter<4, 5, 4>::run(ws, lane_s);
+            atomicAdd(&op.wsum[slot][4 * akq_s + ((lane_s >> 4) & 3)], ws[0]);
             // B e for the thread's 16 k over its NB columns, then over the
             // lanes of the same k-chunk (bits 2..5): lane keeps
             // k = 16 kc + ((lane >> 2) & 15); waves add in LDS.
@@ -243,8 +261,8 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
 #pragma unroll
                     for (int q = 0; q < 4; ++q) vs[4 * d + q] += f[q];
                 }
-            ReduceScatter<16, 5, 2>::run(vs, lane);
-            atomicAdd(&op.vsum[slot][16 * (tid % BKC) + ((lane >> 2) & 15)], vs[0]);
+            ReduceScatter<16, 5, 2>::run(vs, lane_s);
+            atomicAdd(&op.vsum[slot][16 * (tid_s % BKC) + ((lane_s >> 2) & 15)], vs[0]);
         }
     };
 
@@ -331,7 +349,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemFP
             if (t + 2 < nk) load_panels(t + 2, std::integral_constant<int, 1 - H>{});
         }
         if constexpr (FT > 0 && NEXT) {   // slot for step t+2: its last reader finished before this step
-            const int x = tid < BK ? tid : BK - 1;
+            const int tz = OPQ ? opaque_tid() : tid, x = tz < BK ? tz : BK - 1;
             op.wsum[(t + 2) % 3][x] = 0.f;
             op.vsum[(t + 2) % 3][x] = 0.f;
         }
