@@ -326,24 +326,22 @@ template <class G>
 __device__ __forceinline__ void tile_sums(const Acc<G>& acc, CheckLds<G>& s, const Thread& th) {
     constexpr int MI = G::MI, NI = G::NI, TM = G::TM, TN = G::TN;
     const int lane = th.lane, l32 = th.l32, hh = th.hh, wm = th.wm, wn = th.wn;
+    // (every sum starts from its first term: an add to 0.0 is not an exact
+    // no-op for -0.0, so the compiler would keep it)
     float rpart[MI];
-#pragma unroll
-    for (int bi = 0; bi < MI; ++bi) rpart[bi] = 0.f;
 #pragma unroll
     for (int bj = 0; bj < NI; ++bj) {
         float cs[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) cs[r] = 0.f;
 #pragma unroll
         for (int bi = 0; bi < MI; ++bi) {
             float rs = 0.f;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float x = acc[bi][bj][r];
-                cs[r] += x;
-                rs += x;
+                cs[r] = bi == 0 ? x : cs[r] + x;
+                rs = r == 0 ? x : rs + x;
             }
-            rpart[bi] += rs;
+            rpart[bi] = bj == 0 ? rs : rpart[bi] + rs;
         }
         ReduceScatter<16, 4, 0>::run(cs, lane);
         if ((l32 & 1) == 0) {
@@ -412,9 +410,9 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
     __syncthreads();
 
     // (3) residuals, thresholds (the analytic FP32 roundoff bound), flags
-    float sa = 0.f, sb = 0.f;
+    float sa = s.nsum[0][0], sb = s.nsum[1][0];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) { sa += s.nsum[0][w]; sb += s.nsum[1][w]; }
+    for (int w = 1; w < NW; ++w) { sa += s.nsum[0][w]; sb += s.nsum[1][w]; }
     // An Inf or NaN operand in the k prefix makes the norm sums (uniform
     // values) non-finite: nothing is flagged and the tile is reported once.
     const bool finite = __builtin_amdgcn_readfirstlane((__builtin_isfinite(sa) && __builtin_isfinite(sb)) ? 1 : 0) != 0;
@@ -424,17 +422,17 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
     float rres = 0.f, cres = 0.f, taur = 0.f, tauc = 0.f;
     bool rf = false, cf = false;
     if (finite && th.my_row >= 0 && th.my_row < th.mI) {
-        float x = 0.f;
+        float x = s.rowpart[0][th.my_row];
 #pragma unroll
-        for (int w = 0; w < WN; ++w) x += s.rowpart[w][th.my_row];
+        for (int w = 1; w < WN; ++w) x += s.rowpart[w][th.my_row];
         rres = x - Rr;
         taur = base * (float)(kp + th.nJ + 1) * na * sb;
         rf = !(fabsf(rres) <= taur);
     }
     if (finite && th.my_col >= 0 && th.my_col < th.nJ) {
-        float x = 0.f;
+        float x = s.colpart[0][th.my_col];
 #pragma unroll
-        for (int w = 0; w < WM; ++w) x += s.colpart[w][th.my_col];
+        for (int w = 1; w < WM; ++w) x += s.colpart[w][th.my_col];
         cres = x - Sc;
         tauc = base * (float)(kp + th.mI + 1) * nb * sa;
         cf = !(fabsf(cres) <= tauc);

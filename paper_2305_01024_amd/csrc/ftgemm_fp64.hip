@@ -322,11 +322,12 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         // of a lane's column, then lane bits 0..3, then the two wave rows
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) {
-            double x = 0.0;
+            double x = accm[0][bi][0];   // (sums start from their first term: an add to 0.0 is kept for -0.0)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) x += accm[bj][bi][q];
+                for (int q = 0; q < 4; ++q)
+                    if (bj + q > 0) x += accm[bj][bi][q];
             x = swap_sum64<5>(swap_sum64<4>(x));
             if (lg == 0) s.rowpart[wn][64 * wm + 16 * bi + li] = x;
         }
@@ -334,9 +335,9 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                double y = 0.0;
+                double y = accm[bj][0][q];
 #pragma unroll
-                for (int bi = 0; bi < 4; ++bi) y += accm[bj][bi][q];
+                for (int bi = 1; bi < 4; ++bi) y += accm[bj][bi][q];
                 y = row_sum64(y);
                 if (li == 0) s.colpart[wm][64 * wn + 16 * bj + 4 * q + lg] = y;
             }
