@@ -217,6 +217,52 @@ def test_leading_dimensions_and_padding_untouched(h):
     assert np.array_equal(C[m:], C0[m:])
 
 
+@pytest.mark.parametrize("off_a,off_b,pad", [(1, 0, 0), (0, 1, 0), (1, 1, 2), (0, 0, 1)])
+def test_interior_loads_unaligned_operands(h, off_a, off_b, pad):
+    """Whole tiles and whole k-steps with A or B starting 8 bytes past a
+    16-byte boundary (off_* doubles), or an odd leading dimension (pad = 1):
+    the interior panels then take the per-element loads instead of the
+    16-byte ones; the product, clean and with one fault per tile, is the
+    oracle's either way."""
+    import torch
+    m, n, k = 256, 256, 96
+    lda, ldb, ldc = m + pad, k + pad, m
+    A = W.normal64((m, k), 733, 0)
+    B = W.normal64((k, n), 733, 1)
+    Ap = np.zeros((lda, k)); Ap[:m] = A
+    Bp = np.zeros((ldb, n)); Bp[:k] = B
+    # device buffers with the operand `off` doubles past the (256-byte aligned) allocation start
+    bufA = torch.zeros(off_a + lda * k, dtype=torch.float64, device="cuda")
+    bufB = torch.zeros(off_b + ldb * n, dtype=torch.float64, device="cuda")
+    bufA[off_a:] = torch.from_numpy(np.ascontiguousarray(Ap.T).reshape(-1)).cuda()
+    bufB[off_b:] = torch.from_numpy(np.ascontiguousarray(Bp.T).reshape(-1)).cuda()
+    pA = bufA.data_ptr() + 8 * off_a
+    pB = bufB.data_ptr() + 8 * off_b
+    assert (pA % 16 == 8) == (off_a == 1) and (pB % 16 == 8) == (off_b == 1)
+    sites = W.fault_sites(W.rng(733, W.STREAM_SITES), m, n, k, *CFG, 0, payload=1e3, per_tile=1)
+    for inj in (None, sites):
+        dC = torch.zeros((n, ldc), dtype=torch.float64, device="cuda")
+        F.ftgemm_set_injection(h, inj)
+        try:
+            rep = F.ReportBuffer(64)
+            st = F.ftgemm_run_f64(h, m, n, k, 1.0, pA, lda, pB, ldb, 0.0, dC.data_ptr(), ldc, F.FT_CORRECT, 0.0,
+                                  torch.cuda.current_stream().cuda_stream, rep)
+            log = F.ftgemm_get_injection_log(h) if inj is not None else None
+        finally:
+            F.ftgemm_set_injection(h, None)
+        C = _host(dC, m, n)
+        assert st == F.OK
+        assert rel_fro(C, O.gemm(A, B)) <= TOL_F64
+        if inj is None:
+            assert rep.report.n_events == 0
+        else:
+            assert len(log) == len(sites) == 4
+            res, cls, _, bad = replay_against_gpu(A, B, CFG, rep, log, u=O.U_FP64)
+            assert bad == 0
+            assert event_keys(rep.events) == event_keys(res.events)
+            assert rep.report.corrected == 4
+
+
 def test_full_size_8192_sampled_tiles(h):
     """8192^3 N(0,1) A, B, C, alpha = beta = 1, as benchmarked: a clean run
     raises no event and three sampled tiles (two corners, one inside) match
