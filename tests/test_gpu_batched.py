@@ -185,6 +185,51 @@ def test_batched_injection_exact_site_log(h):
         assert rel_fro(bt.result(p), res.C) <= TOL, p
 
 
+def test_batched_fp8_injection_exact_site_log(h):
+    """One additive 1e3 fault in every problem of a batch that holds FP8
+    problems (so the launch runs the instantiation with the FP8 tile): every
+    fault corrected at its site, the event log of each problem equal to the
+    oracle replay's on its decoded operands, C within the FP8 accumulation
+    bound of the replay."""
+    import torch
+    shapes = [(300, 200, 257, "fp8"), (128, 128, 512, "fp8"), (200, 300, 100, "bf16"), (256, 130, 70, "fp8"),
+              (190, 256, 300, "f32"), (513, 129, 65, "fp8"), (96, 96, 640, "fp8"), (64, 200, 128, "f32")]
+    bt = Batch(shapes, 505)
+    F.ftgemm_batched(h, bt.probs, F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream)   # build the plan
+    torch.cuda.synchronize()
+    bt.reset()
+    g = W.rng(505, W.STREAM_SITES)
+    sites = []
+    for p, (m, n, k, dt) in enumerate(shapes):
+        c = F.ftgemm_batched_config(h, p).as_tuple()
+        if dt == "fp8":
+            assert c[:3] == (128, 128, 64)
+        s = W.fault_sites(g, m, n, k, c[0], c[1], c[2], c[3], 1, payload=1e3)
+        s["problem"] = p
+        sites.append(s)
+    sites = np.concatenate(sites)
+    sites = sites[np.lexsort((sites["kstep"], sites["tile_n"], sites["tile_m"], sites["problem"]))]
+    F.ftgemm_set_injection(h, sites)
+    rep = F.ReportBuffer(256)
+    F.ftgemm_batched(h, bt.probs, F.FT_CORRECT, 0.0, torch.cuda.current_stream().cuda_stream, rep)
+    log = F.ftgemm_get_injection_log(h)
+    F.ftgemm_set_injection(h, None)
+    assert len(log) == len(shapes)
+    assert rep.report.corrected == len(shapes) and rep.report.uncorrectable == 0
+    ev = rep.events
+    for p, (m, n, k, dt) in enumerate(shapes):
+        c = F.ftgemm_batched_config(h, p).as_tuple()
+        A, B, C0 = bt.host[p]
+        mine = log[log["problem"] == p]
+        inj = O.make_injections([(int(x["tile_m"]), int(x["tile_n"]), int(x["kstep"]), int(x["row"]),
+                                  int(x["col"]), float(x["old_v"]), float(x["new_v"])) for x in mine])
+        res = O.replay(A, B, O.ReplayConfig(mc=c[0], nc=c[1], ku=c[2], g=c[3], c=float(rep.report.tol_used)),
+                       injections=inj)
+        assert int(np.sum(res.classes["cls"] == O.CLS_MUST)) == 1
+        assert event_keys(ev[ev["problem"] == p]) == event_keys(res.events), p
+        assert rel_fro(bt.result(p), res.C) <= (1e-4 if dt == "fp8" else TOL), p
+
+
 def test_batched_graph_capture_replays(h):
     """The batched call captured into a HIP graph (same problem list as the
     eager call before it): each of several replays, with eager work and
