@@ -194,7 +194,26 @@ struct CheckLds {
     unsigned nchecks;       // checks of this tile so far (cleared at tile start); added to the
                             // launch's counter once, at the end of the tile, so that the loop
                             // carries no global atomic whose completion a later wait would see
+    int nflagged;           // wavefronts that flagged a line at the current check (0 between checks)
 };
+
+// Clears the tile's check state; before the tile's first barrier.  Census
+// entries rest at (0 rows, no first row, 0 columns, no first column).
+template <class G>
+__device__ __forceinline__ void clear_check(CheckLds<G>& s, int tid) {
+    if (tid == 0) {
+        s.tainted = 0;
+        s.nonfinite = 0;
+        s.nchecks = 0;
+        s.nflagged = 0;
+    }
+    if (tid < G::NW) {
+        s.census[tid][0] = 0;
+        s.census[tid][1] = -1;
+        s.census[tid][2] = 0;
+        s.census[tid][3] = -1;
+    }
+}
 
 // Extra LDS of the wavefront-tile check: per wave, the flag census of each
 // check tile it holds owners for, and the checksum values of each check
@@ -450,11 +469,16 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
         const int c = __builtin_amdgcn_readlane(th.my_col, __ffsll((long long)m) - 1);
         fc_w = (fc_w < 0 || c < fc_w) ? c : fc_w;
     }
-    if (lane == 0) {
+    // Only a wavefront with a flag writes its census entry (the others keep
+    // the cleared one) and counts itself in s.nflagged, so the common path
+    // reads one word after the barrier.
+    const bool wave_flagged = (rb | cb) != 0ull;
+    if (lane == 0 && wave_flagged) {
         s.census[th.wave][0] = __popcll(rb);
         s.census[th.wave][1] = fr_w;
         s.census[th.wave][2] = __popcll(cb);
         s.census[th.wave][3] = fc_w;
+        atomicAdd(&s.nflagged, 1);
     }
     if (th.tid == 0) {
         s.nchecks += 1u;
@@ -474,7 +498,9 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
         flogged = fnext;
     }
     __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s.nflagged) == 0) return;
 
+    // rare path: something was flagged (uniform branch)
     int nr = 0, ncl = 0, fr = -1, fc = -1;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -484,9 +510,7 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
         if (r >= 0 && (fr < 0 || r < fr)) fr = r;
         if (c >= 0 && (fc < 0 || c < fc)) fc = c;
     }
-    if (nr + ncl == 0) return;
 
-    // rare path: something was flagged (uniform branch)
     // online level: compile-time in the FT = 2 kernels; the FT = 1 (detect-only)
     // kernels take it from the arguments, so that their code matches the
     // online kernels' and the compiler schedules their loops alike
@@ -527,6 +551,15 @@ __device__ __forceinline__ void check(Acc<G>& acc, CheckLds<G>& s, const LaunchA
         *dst = part;
     }
     __syncthreads();
+    // every thread has read the census: back to the cleared state for the
+    // next check (whose writes come after at least one more barrier)
+    if (lane == 0 && wave_flagged) {
+        s.census[th.wave][0] = 0;
+        s.census[th.wave][1] = -1;
+        s.census[th.wave][2] = 0;
+        s.census[th.wave][3] = -1;
+    }
+    if (th.tid == 0) s.nflagged = 0;
     if (correct) {
         // P_ij = R_i - sum_{j' != j} P_ij'
         float excl = 0.f;

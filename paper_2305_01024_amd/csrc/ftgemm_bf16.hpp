@@ -99,7 +99,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, SmemBF
             (&op.wsum[0][0])[x] = 0.f;
             (&op.vsum[0][0])[x] = 0.f;
         }
-        if (tid == 0) { sm.ck.tainted = 0; sm.ck.nonfinite = 0; sm.ck.nchecks = 0; }
+        clear_check(sm.ck, tid);
     }
     int fnext = 0, flogged = 0;
     if constexpr (INJ) gather_faults<G>(sm.ck, a, th);

@@ -107,7 +107,7 @@ __device__ __forceinline__ void tile(const LaunchArgs& a, int tm, int tn, Smem<B
 
     if constexpr (FT > 0) {
         for (int x = tid; x < 3 * EB * BK; x += NT) (&op.vsum[0][0][0])[x] = 0.f;
-        if (tid == 0) { sm.ck.tainted = 0; sm.ck.nonfinite = 0; sm.ck.nchecks = 0; }
+        clear_check(sm.ck, tid);
     }
     int fnext = 0, flogged = 0;
     if constexpr (INJ) gather_faults<G, WAVE>(sm.ck, a, th);
