@@ -297,19 +297,18 @@ __device__ void tile64(const F64Args& a, int tm, int tn, F64Lds& s) {
             const double y0 = swap_add64<5>(x[0], x[2]), y1 = swap_add64<5>(x[1], x[3]);
             const double w = row_sum64(swap_add64<4>(y0, y1));
             if ((lane & 15) == 0) s.wsum[buf][4 * ((lane >> 4) & 3) + wave] = w;
-            // B e: the thread's 4 columns of its k pair, then the 8 lanes of
-            // the wave with the same k pair (lane bits 3..5), then the waves
-            double v0 = 0.0, v1 = 0.0;
+            // B e: the thread's 4 columns of its k pair, then a reduce-scatter
+            // over the 8 lanes of the wave with the same k pair (lane bits
+            // 3..5): on bit 3 lanes with the bit clear keep k and those with
+            // it set keep k + 1, each adding what its partner l ^ 8 sends;
+            // bits 4 and 5 finish, and the waves add in LDS
+            double v0 = rb[0][0], v1 = rb[0][1];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { v0 += rb[r][0]; v1 += rb[r][1]; }
-            v0 += dpp64<0x128>(v0);   // row_ror:8: exactly l ^ 8 within a row
-            v1 += dpp64<0x128>(v1);
-            v0 = swap_sum64<5>(swap_sum64<4>(v0));
-            v1 = swap_sum64<5>(swap_sum64<4>(v1));
-            if (lane < 8) {
-                atomicAdd(&s.vsum[vslot][2 * lane], v0);
-                atomicAdd(&s.vsum[vslot][2 * lane + 1], v1);
-            }
+            for (int r = 1; r < 4; ++r) { v0 += rb[r][0]; v1 += rb[r][1]; }
+            const bool upper = (lane & 8) != 0;
+            const double keep = upper ? v1 : v0, send = upper ? v0 : v1;
+            const double v = swap_sum64<5>(swap_sum64<4>(keep + dpp64<0x128>(send)));   // row_ror:8 = l ^ 8
+            if (lane < 16) atomicAdd(&s.vsum[vslot][2 * (lane & 7) + ((lane >> 3) & 1)], v);
         }
     };
 
